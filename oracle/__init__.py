@@ -1,0 +1,28 @@
+"""FP64 / exact-integer CPU oracle for the lattice FFT and the fast lattice
+wavelet decomposition (Bergmann, "The fast Fourier Transform and fast Wavelet
+Transform for Patterns on the Torus", arXiv:1107.5415).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The product path (the
+HIP library and its Python binding) never imports, calls or links anything in
+here, and nothing in here imports the product package: the two implementations
+share no code.  The only module both sides read is the seeded input generator
+``workloads``, which holds no arithmetic of the method.
+
+Every function is written from the paper's definitions, in plain and slow
+form (Python integers for all integer work, float64 / complex128 for all
+floating-point work), so that it can be checked against the paper by eye.
+
+Modules
+  lattice  exact integer algebra: det, adjugate, Hermite and Smith invariants,
+           natural residue boxes, symmetric representatives (Section 2.2)
+  dft      the Fourier matrix F(M) as a direct O(m^2) sum (eq. Fouriermatrix)
+           and an independent Hermite-form row/column FFT for large m
+  wavelet  Dirichlet scaling mask (Section 6.2), one-level split and its
+           inverse (Section 5.3, steps 1-5), multi-level pyramid, and the
+           time-domain inner-product definition it must equal
+  grad     float64 torch autograd re-implementation for gradient checks
+
+Parity status of every function is stated in its docstring; functions without
+an independent pin say "parity unpinned".
+"""
