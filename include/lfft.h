@@ -1,0 +1,192 @@
+/*
+ * lfft — lattice FFT and fast lattice wavelet decomposition for AMD MI355X
+ * (gfx950).  C ABI of liblfft.so.
+ *
+ * Method: R. Bergmann, "The fast Fourier Transform and fast Wavelet Transform
+ * for Patterns on the Torus" (arXiv:1107.5415).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - M is a regular integer d x d matrix (1 <= d <= 4), row-major int64,
+ *    m = |det M| < 2^31.  Samples are the points y of the pattern P(M),
+ *    addressed by their integer key g = M y in G(M) = Z^d / M Z^d
+ *    (Section 2.2); frequencies are the classes h of G(M^T).
+ *  - NATURAL order of G(M): the box prod_i [0, H_ii) of the column Hermite
+ *    normal form H = M U (upper triangular, H_ii > 0, 0 <= H_ij < H_ii for
+ *    j > i), enumerated in C order (last coordinate fastest).  NATURAL order
+ *    of G(M^T) uses the Hermite form of M^T.  The paper leaves the order of a
+ *    pattern open (Section 2.2: any complete set of representatives); this
+ *    box is unique for every M.
+ *  - GRID order: the lexicographic order of the coefficient vectors lambda
+ *    (samples) and mu (frequencies) over Z_eps1 x ... x Z_epsd with respect
+ *    to the bases y_j = R^{-1} e_j / eps_j and h_j = R^T e_j of the Smith
+ *    form M = Q diag(eps) R (Section 3, eqs. basisPM, basisGM; eq. orderings
+ *    of Section 4.1).  In this order the Fourier matrix is the Kronecker
+ *    product of 1-D DFTs (Theorem 1) and needs no rearrangement.  Only the
+ *    non-trivial eps_j (> 1) are axes; eps is ascending so the largest cycle
+ *    is the contiguous axis.
+ *  - Data are complex64 (interleaved float re, float im), batch outermost
+ *    with stride m.  Masks are float32.
+ *  - All buffers passed to execute calls are DEVICE pointers owned by the
+ *    caller; the workspace must hold lfft_workspace_size() bytes (may be NULL
+ *    when that size is 0).  Execution is out of place (in != out) and ordered
+ *    on `stream` (NULL = default stream).  Plans are immutable after
+ *    creation and may be used concurrently on different streams only with
+ *    distinct workspaces.
+ *  - Every function returns LFFT_OK (0) or a negative status; no exception
+ *    crosses the ABI.  lfft_strerror() names a status.
+ */
+#ifndef LFFT_H
+#define LFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LFFT_OK 0
+#define LFFT_E_ARG (-1)          /* null/aliased pointer, bad size or flag    */
+#define LFFT_E_SINGULAR (-2)     /* det M = 0                                 */
+#define LFFT_E_NOT_INTEGRAL (-3) /* J^{-1} M not integral at some level       */
+#define LFFT_E_OVERFLOW (-4)     /* exact integer work would exceed int64     */
+#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| != 2, or an
+                                    elementary divisor with a prime factor
+                                    that cannot be split to fit on chip      */
+#define LFFT_E_HIP (-6)          /* a HIP call or kernel launch failed        */
+#define LFFT_E_NOMEM (-7)        /* device table allocation failed            */
+#define LFFT_E_STATE (-8)        /* internal consistency check failed, or an
+                                    execute call on a host-only plan          */
+
+/* ---- plan flags --------------------------------------------------------- */
+#define LFFT_HOST_ONLY 0x1u      /* integer planning only: no device tables,
+                                    execute calls return LFFT_E_STATE         */
+
+/* ---- layouts (bitwise OR of one input and one output choice) ------------ */
+#define LFFT_IN_NATURAL 0x0u
+#define LFFT_IN_GRID 0x1u
+#define LFFT_OUT_NATURAL 0x0u
+#define LFFT_OUT_GRID 0x2u
+
+/* ---- index-map selectors ------------------------------------------------ */
+#define LFFT_MAP_SAMPLES 0       /* lambda = Q^{-1} g mod eps (forward basis) */
+#define LFFT_MAP_FREQS 1         /* mu = R^{-T} h mod eps (forward basis)     */
+#define LFFT_MAP_SAMPLES_T 2     /* same for M^T in the inverse basis         */
+#define LFFT_MAP_FREQS_T 3
+
+typedef struct lfft_plan_s* lfft_plan_t;
+typedef struct lwt_plan_s* lwt_plan_t;
+
+/* Create a lattice-FFT plan for M (row-major d x d) and `batch` signals.
+ * Does all integer work on the host, exactly (Section 2.2 Smith form
+ * eq. SNF and Hermite boxes; Section 3 bases; Section 4.1 Theorem 1 and
+ * Remark 1 for the basis choice) and, unless LFFT_HOST_ONLY, uploads the
+ * index and twiddle tables to the current HIP device.  *plan receives the
+ * handle (NULL on error).  Errors: ARG, SINGULAR, OVERFLOW, UNSUPPORTED,
+ * NOMEM, HIP. */
+int lfft_plan_create(lfft_plan_t* plan, int d, const int64_t* M, int64_t batch, uint32_t flags);
+
+/* Release a plan and its device tables (NULL is accepted). */
+int lfft_plan_destroy(lfft_plan_t plan);
+
+/* Integer data of the plan (host outputs, any may be NULL):
+ * m; d_M = number of eps_j > 1 (Section 2.2); eps[d] ascending with
+ * eps_j | eps_{j+1}; Q, R (d x d row-major, unimodular, M = Q diag(eps) R,
+ * the forward basis); H_M, H_MT (column Hermite forms of M and M^T). */
+int lfft_plan_query(lfft_plan_t plan, int64_t* m, int* d_M, int64_t* eps, int64_t* Q, int64_t* R,
+                    int64_t* H_M, int64_t* H_MT);
+
+/* Smith factors M^T = Qt diag(eps) Rt of the basis used by the
+ * natural-to-natural inverse (host outputs, d x d row-major each). */
+int lfft_plan_query_inverse_basis(lfft_plan_t plan, int64_t* Qt, int64_t* Rt);
+
+/* Number of device passes per transform and whether each basis has its
+ * largest cycle aligned with the last sample coordinate (host outputs). */
+int lfft_plan_info(lfft_plan_t plan, int* passes, int* aligned_forward, int* aligned_inverse);
+
+/* Host array natural_to_grid[m]: the GRID linear index of every NATURAL
+ * index for the selected LFFT_MAP_* (Section 3, eqs. basisPM/basisGM:
+ * lambda = Q^{-1} g mod eps, mu = R^{-T} h mod eps).  Bijective. */
+int lfft_index_map(lfft_plan_t plan, int which, int64_t* natural_to_grid);
+
+/* Workspace bytes needed by lfft_forward / lfft_inverse. */
+size_t lfft_workspace_size(lfft_plan_t plan);
+
+/* Unitary lattice DFT  out = F(M) in  (Section 2.2, eq. Fouriermatrix):
+ *   out_h = m^{-1/2} sum_g in_g exp(-2 pi i h^T M^{-1} g).
+ * in: device complex64 [batch][m] in the selected input order (samples);
+ * out: device complex64 [batch][m] (frequencies). */
+int lfft_forward(lfft_plan_t plan, const void* in, void* out, void* workspace, uint32_t layout,
+                 hipStream_t stream);
+
+/* Inverse (= conjugate transpose) of lfft_forward: in are frequencies,
+ * out are samples. */
+int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, uint32_t layout,
+                 hipStream_t stream);
+
+/* ---- fast wavelet decomposition (Section 5.3) --------------------------- */
+
+/* Plan `levels` dyadic steps M_1 = M, N_l = J^{-1} M_l, M_{l+1} = N_l for a
+ * dilation J with |det J| = 2 (Section 5.3; Section 6.2 Dirichlet wavelets)
+ * and `batch` signals.  Errors: ARG, SINGULAR, NOT_INTEGRAL, OVERFLOW,
+ * UNSUPPORTED (|det J| != 2), NOMEM, HIP. */
+int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J, int levels,
+                    int64_t batch, uint32_t flags);
+int lwt_plan_destroy(lwt_plan_t plan);
+
+/* Level l (0-based) data: N_l (d x d row-major), m_l = |det M_l|, the
+ * elementary divisors of N_l (host outputs, any may be NULL). */
+int lwt_level_info(lwt_plan_t plan, int level, int64_t* N, int64_t* m_level, int64_t* eps_N);
+
+/* Dirichlet scaling mask of level l (Section 6.2): host float[m_l] in
+ * NATURAL order of G(M_l^T); values 2^{(1 + r_M - r_N)/2} on the closed
+ * N_l-box of symmetric representatives, 0 elsewhere. */
+int lwt_dirichlet_mask(lwt_plan_t plan, int level, float* mask);
+
+/* Workspace bytes of every lwt_* execute call, and complex64 elements of
+ * the `saved` buffer used for differentiation. */
+size_t lwt_workspace_size(lwt_plan_t plan);
+size_t lwt_saved_elems(lwt_plan_t plan);
+
+/* Decomposition (Section 5.3, steps 1-5, levels chained through the
+ * low-pass Fourier data): samples [batch][m] NATURAL order of G(M) ->
+ * coeffs [batch][m] = [d2^(1) | ... | d2^(L) | d1^(L)], block l in NATURAL
+ * order of G(N_l).  masks: host array of `levels` device pointers, mask l
+ * float[m_l] in NATURAL order of G(M_l^T) (real scaling symbol; the wavelet
+ * symbol is derived from it).  saved: NULL or device complex64 buffer of
+ * lwt_saved_elems() receiving the per-level Fourier inputs (needed by
+ * lwt_decompose_backward for mask gradients). */
+int lwt_decompose(lwt_plan_t plan, const void* samples, const float* const* masks, void* coeffs,
+                  void* saved, void* workspace, hipStream_t stream);
+
+/* Reconstruction (inverse of lwt_decompose; synthesis gamma = sum_j sum_y
+ * d_{j,y} T(y) g_j of Section 5.3).  saved: NULL or buffer of
+ * lwt_saved_elems() receiving the per-level (d1hat, d2hat) for
+ * lwt_reconstruct_backward. */
+int lwt_reconstruct(lwt_plan_t plan, const void* coeffs, const float* const* masks, void* samples,
+                    void* saved, void* workspace, hipStream_t stream);
+
+/* Adjoint of lwt_decompose: grad_samples = D^H grad_coeffs, and, if
+ * grad_masks (host array of device pointers) is non-NULL, d loss / d mask_l
+ * summed over the batch, using `saved` from lwt_decompose. */
+int lwt_decompose_backward(lwt_plan_t plan, const void* grad_coeffs, const void* saved,
+                           const float* const* masks, void* grad_samples, float* const* grad_masks,
+                           void* workspace, hipStream_t stream);
+
+/* Adjoint of lwt_reconstruct, with mask gradients from its `saved`. */
+int lwt_reconstruct_backward(lwt_plan_t plan, const void* grad_samples, const void* saved,
+                             const float* const* masks, void* grad_coeffs,
+                             float* const* grad_masks, void* workspace, hipStream_t stream);
+
+/* Static description of a status code. */
+const char* lfft_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFFT_H */

@@ -1,0 +1,77 @@
+// Plain-old-data descriptors handed from the host planner to the gfx950
+// kernels by value.  All pointers are device pointers into the plan's table
+// blob.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lfft {
+
+constexpr int kMaxStages = 24;
+
+// How a pass addresses the buffer on one side.
+//   IDENTITY : the internal grid layout, index = ((b*O + o)*L + l)*S + s
+//   LINEAR   : separable offsets, index = b*bstride + To[o].x + Tl[l].x + Ts[s].x
+//   NATURAL  : natural residue box of a lattice (column Hermite form H):
+//              coords = To[o] (+) Tl[l] (+) Ts[s]  (group sum in Z^d / H Z^d),
+//              index  = b*bstride + sum_i coords_i * box_stride_i
+enum MapMode : int { MAP_IDENTITY = 0, MAP_LINEAR = 1, MAP_NATURAL = 2 };
+
+struct MapDesc {
+  int mode;
+  int d;
+  int H[4][4];
+  long long box_stride[4];
+  long long bstride;          // batch stride in elements (LINEAR / NATURAL)
+  const int4* To;
+  const int4* Tl;
+  const int4* Ts;
+};
+
+// One Stockham stage: radix r on the pass digit of length n whose stride
+// inside the pencil index l is `stride`; Ns is the product of the radices
+// already applied to that digit.  tw[k] = exp(-2 pi i k / n), k in [0, n).
+struct StageDesc {
+  int radix;
+  int n;
+  int stride;
+  int Ns;
+  const float2* tw;
+};
+
+struct PassDesc {
+  long long batch;            // number of signals
+  int O, L, S;                // per-signal outer count, pencil length, inner count
+  int TP;                     // pencils per tile
+  int nst;
+  StageDesc st[kMaxStages];
+  int sign;                   // -1 forward, +1 inverse
+  float scale;                // applied when storing
+  // four-step twiddle after the stages: x = (l * lo) mod postN with
+  // lo = (s / lo_div) % lo_n, factor exp(sign 2 pi i x / postN) from the
+  // two-level table tw_hi[x >> 12] * tw_lo[x & 4095]
+  int post;
+  int postN;
+  int lo_div;
+  int lo_n;
+  const float2* tw_hi;
+  const float2* tw_lo;
+  MapDesc in, out;
+};
+
+// One level of the Fourier-domain wavelet split (natural orders).
+struct SplitDesc {
+  long long mM;               // |det M_l| (points of the level)
+  long long mN;               // |det N_l| = mM / 2
+  int d;
+  int KN[4];                  // natural box of N_l^T (Hermite diagonal)
+  long long kstride[4];
+  int HM[4][4];               // column Hermite form of M_l^T
+  long long hstride[4];
+  int s[4];                   // s = N_l^T g0 reduced into the M_l^T box
+  int w[4];                   // phase weights: phi(h) = exp(-2 pi i (w.h mod E)/E)
+  int E;                      // phase modulus (largest elementary divisor of M_l)
+  const float2* tw;           // exp(-2 pi i t / E), t in [0, E)
+};
+
+}  // namespace lfft

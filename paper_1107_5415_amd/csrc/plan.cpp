@@ -1,0 +1,742 @@
+// Host planner: Smith bases, pass schedules, index tables and twiddles.
+//
+// The lattice DFT (Section 2.2, eq. Fouriermatrix) becomes a dense
+// multi-dimensional DFT over the grid Z_eps1 x ... x Z_epsd once samples and
+// frequencies are addressed through a pair of biorthogonal bases (Section 3,
+// eqs. basisPM/basisGM, Lemma 1; Theorem 1 and Remark 1 of Section 4.1).
+// All integer work happens here, exactly; the kernels only add reduced
+// coordinate vectors and look up FP32 twiddles built in FP64.
+#include "plan.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "kernels.hpp"
+
+namespace lfft {
+
+namespace {
+constexpr i64 kMaxPencil = 8192;   // longest digit handled on chip
+constexpr i64 kMaxTile = 8192;     // elements of one single-pass tile
+constexpr i64 kTileTarget = 4096;  // elements per tile for short pencils
+
+Vec4 zero4() { return Vec4{0, 0, 0, 0}; }
+
+Vec4 reduce4(const Mat& H, Vec4 v) {
+  reduce_box(H, v.data());
+  return v;
+}
+
+Vec4 add4(const Mat& H, const Vec4& a, const Vec4& b) {
+  Vec4 c;
+  for (int i = 0; i < 4; ++i) c[i] = cadd(a[i], b[i]);
+  return reduce4(H, c);
+}
+
+Vec4 scale4(const Mat& H, const Vec4& u, i64 k) {
+  Vec4 c;
+  for (int i = 0; i < 4; ++i) c[i] = cmul(u[i], k);
+  return reduce4(H, c);
+}
+
+std::vector<int> nontrivial_axes(const Smith& S) {
+  std::vector<int> t;
+  for (int i = 0; i < S.d; ++i)
+    if (S.eps[i] > 1) t.push_back(i);
+  return t;
+}
+
+// Sample side of basis S on lattice A: natural box of A, unit steps Q e_t.
+Side sample_side(const Smith& S, const Mat& A) {
+  Side s;
+  Mat U;
+  hnf(A, s.H, U);
+  for (int t : nontrivial_axes(S)) {
+    Vec4 u = zero4();
+    for (int i = 0; i < S.d; ++i) u[i] = S.Q.a[i][t];
+    s.unit.push_back(reduce4(s.H, u));
+  }
+  return s;
+}
+
+// Frequency side of basis S on lattice A: natural box of A^T, unit steps R^T e_t.
+Side freq_side(const Smith& S, const Mat& A) {
+  Side s;
+  Mat U;
+  hnf(transpose(A), s.H, U);
+  for (int t : nontrivial_axes(S)) {
+    Vec4 u = zero4();
+    for (int i = 0; i < S.d; ++i) u[i] = S.R.a[t][i];
+    s.unit.push_back(reduce4(s.H, u));
+  }
+  return s;
+}
+
+std::vector<int> radices_of(i64 n) {
+  std::vector<int> r;
+  while (n % 16 == 0 && n > 16 * 1) {
+    r.push_back(16);
+    n /= 16;
+  }
+  // remaining power of two as one radix from {2,4,8,16}
+  if (n % 16 == 0) {
+    r.push_back(16);
+    n /= 16;
+  } else if (n % 8 == 0) {
+    r.push_back(8);
+    n /= 8;
+  } else if (n % 4 == 0) {
+    r.push_back(4);
+    n /= 4;
+  } else if (n % 2 == 0) {
+    r.push_back(2);
+    n /= 2;
+  }
+  for (i64 p = 3; n > 1; p += 2) {
+    while (n % p == 0) {
+      r.push_back((int)p);
+      n /= p;
+    }
+    if (p * p > n && n > 1) {
+      r.push_back((int)n);
+      n = 1;
+    }
+  }
+  return r;
+}
+
+struct TwCache {
+  Blob* blob;
+  std::map<i64, const float2*> full;
+  std::map<i64, std::pair<const float2*, const float2*>> two;
+  const float2* table(i64 n) {
+    auto it = full.find(n);
+    if (it != full.end()) return it->second;
+    std::vector<float2> t(n);
+    for (i64 k = 0; k < n; ++k) {
+      // exact residue k/n; angle reduced by symmetry in double precision
+      double a = -2.0 * M_PI * (double)k / (double)n;
+      t[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    const float2* p = blob->ref(t);
+    full[n] = p;
+    return p;
+  }
+  std::pair<const float2*, const float2*> twolevel(i64 N) {
+    auto it = two.find(N);
+    if (it != two.end()) return it->second;
+    std::vector<float2> lo(4096), hi((N + 4095) / 4096);
+    for (i64 k = 0; k < 4096; ++k) {
+      double a = -2.0 * M_PI * (double)(k % N) / (double)N;
+      lo[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    for (i64 k = 0; k < (i64)hi.size(); ++k) {
+      double a = -2.0 * M_PI * (double)((k * 4096) % N) / (double)N;
+      hi[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    auto pr = std::make_pair(blob->ref(hi), blob->ref(lo));
+    two[N] = pr;
+    return pr;
+  }
+};
+
+struct TableSpec {
+  const std::vector<Digit>* digits;
+  int a, b;  // digit range enumerated in C order
+};
+
+i64 range_count(const std::vector<Digit>& dg, int a, int b) {
+  i64 c = 1;
+  for (int g = a; g < b; ++g) c *= dg[g].n;
+  return c;
+}
+
+// natural coordinates of every index of the digit range [a, b)
+std::vector<int4> natural_table(const Side& side, const std::vector<Digit>& dg, int a, int b,
+                                bool out_weights) {
+  i64 cnt = range_count(dg, a, b);
+  std::vector<int4> t(cnt);
+  std::vector<i64> val(dg.size(), 0);
+  for (i64 idx = 0; idx < cnt; ++idx) {
+    i64 r = idx;
+    for (int g = b - 1; g >= a; --g) {
+      val[g] = r % dg[g].n;
+      r /= dg[g].n;
+    }
+    Vec4 c = zero4();
+    for (int g = a; g < b; ++g) {
+      i64 w = out_weights ? dg[g].w_out : dg[g].w_in;
+      c = add4(side.H, c, scale4(side.H, side.unit[dg[g].axis], cmul(val[g], w)));
+    }
+    t[idx] = make_int4((int)c[0], (int)c[1], (int)c[2], (int)c[3]);
+  }
+  return t;
+}
+
+// linear grid offsets (output weights) of every index of the digit range
+std::vector<int4> linear_table(const std::vector<i64>& eps, const std::vector<Digit>& dg, int a,
+                               int b) {
+  std::vector<i64> gstride(eps.size(), 1);
+  for (int j = (int)eps.size() - 2; j >= 0; --j) gstride[j] = gstride[j + 1] * eps[j + 1];
+  i64 cnt = range_count(dg, a, b);
+  std::vector<int4> t(cnt);
+  for (i64 idx = 0; idx < cnt; ++idx) {
+    i64 r = idx, off = 0;
+    for (int g = b - 1; g >= a; --g) {
+      i64 v = r % dg[g].n;
+      r /= dg[g].n;
+      off += v * dg[g].w_out * gstride[dg[g].axis];
+    }
+    t[idx] = make_int4((int)off, 0, 0, 0);
+  }
+  return t;
+}
+
+MapDesc natural_map(Blob& blob, const Side& side, int d, const std::vector<Digit>& dg, int a,
+                    int b, bool out_weights) {
+  MapDesc m{};
+  m.mode = MAP_NATURAL;
+  m.d = d;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) m.H[i][j] = (i < d && j < d) ? (int)side.H.a[i][j] : 0;
+  i64 st = 1;
+  for (int i = d - 1; i >= 0; --i) {
+    m.box_stride[i] = st;
+    st *= side.H.a[i][i];
+  }
+  for (int i = d; i < 4; ++i) m.box_stride[i] = 0;
+  m.To = blob.ref(natural_table(side, dg, 0, a, out_weights));
+  m.Tl = blob.ref(natural_table(side, dg, a, b, out_weights));
+  m.Ts = blob.ref(natural_table(side, dg, b, (int)dg.size(), out_weights));
+  return m;
+}
+
+MapDesc identity_map() {
+  MapDesc m{};
+  m.mode = MAP_IDENTITY;
+  return m;
+}
+
+void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& out_side, int sign,
+                  TwCache& tw) {
+  E.sign = sign;
+  const auto& dg = p->digits;
+  const int D = (int)dg.size();
+  const int np = (int)p->ranges.size();
+  bool any_split = false;
+  for (auto& g : dg) any_split |= (g.part != 0);
+  for (int pi = 0; pi < np; ++pi) {
+    const PassRange& R = p->ranges[pi];
+    PassDesc pd{};
+    pd.batch = p->batch;
+    pd.O = (int)range_count(dg, 0, R.a);
+    pd.L = (int)range_count(dg, R.a, R.b);
+    pd.S = (int)range_count(dg, R.b, D);
+    i64 tp = std::max<i64>(1, kTileTarget / pd.L);
+    if (pd.S > 1) {
+      tp = std::min<i64>(tp, pd.S);
+      while (pd.S % tp) --tp;
+    }
+    pd.TP = (int)tp;
+    pd.nst = 0;
+    for (int g = R.a; g < R.b; ++g) {
+      int stride = (int)range_count(dg, g + 1, R.b);
+      i64 Ns = 1;
+      for (int r : radices_of(dg[g].n)) {
+        if (pd.nst >= kMaxStages) throw StatusError{E_UNSUPPORTED};
+        StageDesc& s = pd.st[pd.nst++];
+        s.radix = r;
+        s.n = (int)dg[g].n;
+        s.stride = stride;
+        s.Ns = (int)Ns;
+        s.tw = tw.table(dg[g].n);
+        Ns *= r;
+      }
+    }
+    pd.sign = sign;
+    pd.scale = (pi == np - 1) ? (float)(1.0 / std::sqrt((double)p->m)) : 1.0f;
+    pd.post = R.post ? 1 : 0;
+    if (R.post) {
+      // this pass is the high digit a; the low digit is a + 1
+      i64 N = dg[R.a].n * dg[R.a + 1].n;
+      pd.postN = (int)N;
+      pd.lo_n = (int)dg[R.a + 1].n;
+      pd.lo_div = (int)range_count(dg, R.a + 2, D);
+      auto pr = tw.twolevel(N);
+      pd.tw_hi = pr.first;
+      pd.tw_lo = pr.second;
+    }
+    pd.in = identity_map();
+    pd.out = identity_map();
+    E.passes.push_back(pd);
+  }
+  // map variants of the first and the last pass
+  const PassRange& R0 = p->ranges.front();
+  const PassRange& R1 = p->ranges.back();
+  E.in_grid = identity_map();
+  E.in_nat = natural_map(p->blob, in_side, p->d, dg, R0.a, R0.b, false);
+  E.has_nat_in = true;
+  if (any_split) {
+    MapDesc m{};
+    m.mode = MAP_LINEAR;
+    m.To = p->blob.ref(linear_table(p->eps, dg, 0, R1.a));
+    m.Tl = p->blob.ref(linear_table(p->eps, dg, R1.a, R1.b));
+    m.Ts = p->blob.ref(linear_table(p->eps, dg, R1.b, D));
+    E.out_grid = m;
+  } else {
+    E.out_grid = identity_map();
+  }
+  E.out_nat = natural_map(p->blob, out_side, p->d, dg, R1.a, R1.b, true);
+  E.has_nat_out = true;
+}
+
+template <class T>
+void patch(T*& ptr, uintptr_t base) {
+  if (ptr) ptr = reinterpret_cast<T*>(base + reinterpret_cast<uintptr_t>(ptr) - 1);
+}
+
+void patch_map(MapDesc& m, uintptr_t base) {
+  patch(m.To, base);
+  patch(m.Tl, base);
+  patch(m.Ts, base);
+}
+
+void patch_engine(Engine& E, uintptr_t base) {
+  for (auto& pd : E.passes) {
+    for (int i = 0; i < pd.nst; ++i) patch(pd.st[i].tw, base);
+    patch(pd.tw_hi, base);
+    patch(pd.tw_lo, base);
+    patch_map(pd.in, base);
+    patch_map(pd.out, base);
+  }
+  patch_map(E.in_nat, base);
+  patch_map(E.in_grid, base);
+  patch_map(E.out_nat, base);
+  patch_map(E.out_grid, base);
+}
+
+void* upload_blob(const Blob& b) {
+  if (b.bytes.empty()) return nullptr;
+  void* d = nullptr;
+  if (hipMalloc(&d, b.bytes.size()) != hipSuccess) throw StatusError{E_NOMEM};
+  if (hipMemcpy(d, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    throw StatusError{E_HIP};
+  }
+  return d;
+}
+}  // namespace
+
+size_t Blob::add(const void* p, size_t n) {
+  size_t off = (bytes.size() + 255) & ~size_t(255);
+  bytes.resize(off + std::max<size_t>(n, 1));
+  if (n) std::memcpy(bytes.data() + off, p, n);
+  return off;
+}
+
+LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags) {
+  if (d < 1 || d > kMaxD || !Mrm || batch < 1) throw StatusError{E_ARG};
+  auto* p = new LatticePlan();
+  try {
+    p->d = d;
+    p->M = Mat::from(d, Mrm);
+    p->batch = batch;
+    p->flags = flags;
+    i64 D = det(p->M);
+    if (D == 0) throw StatusError{E_SINGULAR};
+    p->m = D < 0 ? -D : D;
+    if (p->m >= (i64(1) << 31)) throw StatusError{E_UNSUPPORTED};
+    if (cmul(p->m, batch) >= (i64(1) << 40)) throw StatusError{E_UNSUPPORTED};
+    hnf(p->M, p->HM, p->UM);
+    hnf(transpose(p->M), p->HMT, p->UMT);
+    p->Sf = smith(p->M);
+    p->Sf_aligned = align_last_cycle(p->Sf, p->M, d - 1);
+    p->Si = smith(transpose(p->M));
+    p->Si_aligned = align_last_cycle(p->Si, transpose(p->M), d - 1);
+    for (int i = 0; i < d; ++i)
+      if (p->Sf.eps[i] > 1) p->eps.push_back(p->Sf.eps[i]);
+    // digits
+    if (p->eps.empty()) {
+      p->digits.push_back(Digit{0, 1, 0, 1, 1});
+    } else {
+      for (int j = 0; j < (int)p->eps.size(); ++j) {
+        i64 n = p->eps[j];
+        if (n <= kMaxPencil || p->m <= kMaxTile) {
+          if (n > kMaxTile) throw StatusError{E_UNSUPPORTED};
+          p->digits.push_back(Digit{j, n, 0, 1, 1});
+        } else {
+          i64 lo = 0;
+          for (i64 c = kMaxPencil; c >= 2; --c)
+            if (n % c == 0 && n / c <= kMaxPencil) {
+              lo = c;
+              break;
+            }
+          if (!lo) throw StatusError{E_UNSUPPORTED};
+          i64 hi = n / lo;
+          p->digits.push_back(Digit{j, hi, 1, lo, 1});
+          p->digits.push_back(Digit{j, lo, 2, 1, hi});
+        }
+      }
+    }
+    const int Dg = (int)p->digits.size();
+    if (p->m <= kMaxTile) {
+      p->ranges.push_back(PassRange{0, Dg, false, 0});
+    } else {
+      int i = Dg - 1;
+      while (i >= 0) {
+        if (p->digits[i].part == 2) {
+          p->ranges.push_back(PassRange{i - 1, i, true, p->digits[i].axis});
+          p->ranges.push_back(PassRange{i, i + 1, false, 0});
+          i -= 2;
+        } else {
+          int a = i;
+          i64 prod = p->digits[i].n;
+          while (a - 1 >= 0 && p->digits[a - 1].part == 0 && prod * p->digits[a - 1].n <= kMaxPencil) {
+            --a;
+            prod *= p->digits[a].n;
+          }
+          p->ranges.push_back(PassRange{a, i + 1, false, 0});
+          i = a - 1;
+        }
+      }
+    }
+    p->ws_elems = p->ranges.size() > 1 ? (size_t)(p->m * batch) : 0;
+    TwCache tw{&p->blob, {}, {}};
+    Side fs = sample_side(p->Sf, p->M);
+    Side ff = freq_side(p->Sf, p->M);
+    Mat MT = transpose(p->M);
+    Side is = sample_side(p->Si, MT);
+    Side iff = freq_side(p->Si, MT);
+    if (p->eps.empty()) {
+      fs.unit.assign(1, zero4());
+      ff.unit.assign(1, zero4());
+      is.unit.assign(1, zero4());
+      iff.unit.assign(1, zero4());
+    }
+    // the inverse basis must have the same grid (same elementary divisors)
+    for (int i = 0; i < d; ++i)
+      if (p->Si.eps[i] != p->Sf.eps[i]) throw StatusError{E_STATE};
+    build_engine(p, p->fwd, fs, ff, -1, tw);
+    build_engine(p, p->inv_grid, ff, fs, +1, tw);
+    build_engine(p, p->inv_nat, is, iff, +1, tw);
+  } catch (const StatusError&) {
+    delete p;
+    throw;
+  } catch (const IntOverflow&) {
+    delete p;
+    throw StatusError{E_OVERFLOW};
+  } catch (const SingularMatrix&) {
+    delete p;
+    throw StatusError{E_SINGULAR};
+  } catch (const NotIntegral&) {
+    delete p;
+    throw StatusError{E_STATE};
+  }
+  return p;
+}
+
+void upload_plan(LatticePlan* p) {
+  if (p->dtab) return;
+  p->dtab = upload_blob(p->blob);
+  uintptr_t base = reinterpret_cast<uintptr_t>(p->dtab);
+  patch_engine(p->fwd, base);
+  patch_engine(p->inv_grid, base);
+  patch_engine(p->inv_nat, base);
+}
+
+void free_plan(LatticePlan* p) {
+  if (!p) return;
+  if (p->dtab) (void)hipFree(p->dtab);
+  delete p;
+}
+
+void natural_to_grid(const LatticePlan* p, int which, i64* out) {
+  // which: 0 samples (forward basis), 1 freqs (forward basis),
+  //        2 samples of M^T (inverse basis), 3 freqs of M^T (inverse basis)
+  const Smith& S = (which < 2) ? p->Sf : p->Si;
+  bool freq = (which % 2) == 1;
+  const Mat& H = ((which == 0) || (which == 3)) ? p->HM : p->HMT;
+  const int d = p->d;
+  std::vector<int> t = nontrivial_axes(S);
+  i64 cnt = p->m;
+  std::vector<i64> v(d, 0);
+  for (i64 idx = 0; idx < cnt; ++idx) {
+    i64 r = idx;
+    for (int i = d - 1; i >= 0; --i) {
+      v[i] = r % H.a[i][i];
+      r /= H.a[i][i];
+    }
+    i64 lin = 0;
+    for (int tj : t) {
+      i128 acc = 0;
+      for (int i = 0; i < d; ++i) {
+        // lambda = Q^{-1} g ; mu = R^{-T} h  (row t of R^{-T} = column t of R^{-1})
+        i64 c = freq ? S.Rinv.a[i][tj] : S.Qinv.a[tj][i];
+        acc += (i128)c * v[i];
+      }
+      i64 e = S.eps[tj];
+      i64 x = (i64)(acc % e);
+      if (x < 0) x += e;
+      lin = lin * e + x;
+    }
+    out[idx] = lin;
+  }
+}
+
+void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid, const void* in,
+                  void* out, void* ws, long long bin, long long bout, hipStream_t s) {
+  const Engine& E = !inverse ? p->fwd : ((in_grid || out_grid) ? p->inv_grid : p->inv_nat);
+  const int np = (int)E.passes.size();
+  for (int i = 0; i < np; ++i) {
+    PassDesc pd = E.passes[i];
+    const float2* src = (i == 0) ? static_cast<const float2*>(in) : static_cast<const float2*>(ws);
+    float2* dst = (i == np - 1) ? static_cast<float2*>(out) : static_cast<float2*>(ws);
+    pd.in.bstride = p->m;
+    pd.out.bstride = p->m;
+    if (i == 0) {
+      pd.in = in_grid ? E.in_grid : E.in_nat;
+      pd.in.bstride = bin;
+    }
+    if (i == np - 1) {
+      pd.out = out_grid ? E.out_grid : E.out_nat;
+      pd.out.bstride = bout;
+    }
+    hipError_t e = launch_pass(pd, src, dst, s);
+    if (e != hipSuccess) throw StatusError{E_HIP};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wavelet plans (Section 5.3)
+
+namespace {
+// (g0, y0 numerators, v) for |det J| = 2: g0 a unit vector outside J^T Z^d,
+// y0 = num/2 the non-zero point of P(J) in [-1/2, 1/2)^d, v = J y0.
+void dilation_data(const Mat& J, Vec4& g0, Vec4& v) {
+  const int d = J.d;
+  i64 DJ = det(J);
+  Mat adj = adjugate(J);
+  Mat adjT = adjugate(transpose(J));
+  g0 = zero4();
+  bool found = false;
+  for (int i = 0; i < d && !found; ++i) {
+    // J^{-T} e_i = adj(J^T) e_i / det J
+    for (int r = 0; r < d; ++r)
+      if (adjT.a[r][i] % DJ != 0) {
+        g0[i] = 1;
+        found = true;
+        break;
+      }
+  }
+  if (!found) throw StatusError{E_STATE};
+  Vec4 num = zero4();
+  found = false;
+  for (int i = 0; i < d && !found; ++i) {
+    bool nonint = false;
+    for (int r = 0; r < d; ++r)
+      if (adj.a[r][i] % DJ != 0) nonint = true;
+    if (!nonint) continue;
+    // y = adj(J) e_i / det J = (sgn * adj(J) e_i) / 2; reduce numerator into [-1, 1)
+    i64 sg = DJ < 0 ? -1 : 1;
+    for (int r = 0; r < d; ++r) {
+      i64 n = sg * adj.a[r][i];
+      n = posmod(n, 2);          // 0 or 1  ->  y in {0, 1/2}
+      num[r] = n == 1 ? -1 : 0;  // 1/2 == -1/2 (mod 1), and [-1/2, 1/2) holds -1/2
+    }
+    found = true;
+  }
+  if (!found) throw StatusError{E_STATE};
+  v = zero4();
+  for (int r = 0; r < d; ++r) {
+    i64 acc = 0;
+    for (int c = 0; c < d; ++c) acc = cadd(acc, cmul(J.a[r][c], num[c]));
+    if (acc % 2 != 0) throw StatusError{E_STATE};
+    v[r] = acc / 2;
+  }
+}
+}  // namespace
+
+WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64 batch,
+                          uint32_t flags) {
+  if (d < 1 || d > kMaxD || !Mrm || !Jrm || levels < 1 || batch < 1) throw StatusError{E_ARG};
+  auto* w = new WavePlan();
+  try {
+    w->d = d;
+    w->M = Mat::from(d, Mrm);
+    w->J = Mat::from(d, Jrm);
+    w->levels = levels;
+    w->batch = batch;
+    i64 DJ = det(w->J);
+    if (DJ != 2 && DJ != -2) throw StatusError{E_UNSUPPORTED};
+    i64 DM = det(w->M);
+    if (DM == 0) throw StatusError{E_SINGULAR};
+    w->m = DM < 0 ? -DM : DM;
+    w->fftM = build_lattice_plan(d, Mrm, batch, flags);
+    Vec4 g0, v;
+    dilation_data(w->J, g0, v);
+    TwCache tw{&w->blob, {}, {}};
+    Mat Ml = w->M;
+    for (int l = 0; l < levels; ++l) {
+      WaveLevel L;
+      L.Ml = Ml;
+      try {
+        L.Nl = left_quotient(w->J, Ml);
+      } catch (const NotIntegral&) {
+        throw StatusError{E_NOT_INTEGRAL};
+      }
+      i64 dm = det(Ml);
+      L.ml = dm < 0 ? -dm : dm;
+      if (L.ml % 2 != 0) throw StatusError{E_NOT_INTEGRAL};
+      i64 nrm[16];
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) nrm[i * d + j] = L.Nl.a[i][j];
+      L.fftN = build_lattice_plan(d, nrm, batch, flags);
+      // split descriptor
+      SplitDesc& sd = L.sd;
+      sd.mM = L.ml;
+      sd.mN = L.ml / 2;
+      sd.d = d;
+      Mat HN, UN, HMt, UMt;
+      hnf(transpose(L.Nl), HN, UN);
+      hnf(transpose(Ml), HMt, UMt);
+      i64 st = 1;
+      for (int i = d - 1; i >= 0; --i) {
+        sd.KN[i] = (int)HN.a[i][i];
+        sd.kstride[i] = st;
+        st *= HN.a[i][i];
+      }
+      st = 1;
+      for (int i = d - 1; i >= 0; --i) {
+        sd.hstride[i] = st;
+        st *= HMt.a[i][i];
+      }
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) sd.HM[i][j] = (i < d && j < d) ? (int)HMt.a[i][j] : 0;
+      for (int i = d; i < 4; ++i) sd.KN[i] = 1, sd.kstride[i] = 0, sd.hstride[i] = 0;
+      // s = N^T g0
+      Vec4 s = zero4();
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) s[i] = cadd(s[i], cmul(L.Nl.a[j][i], g0[j]));
+      s = reduce4(HMt, s);
+      for (int i = 0; i < 4; ++i) sd.s[i] = (int)s[i];
+      // phase: h^T M^{-1} v = (sgn adj(M) v . h) / m ; E = largest eps of M
+      Smith Sm = smith(Ml);
+      i64 E = 1;
+      for (int i = 0; i < d; ++i) E = std::max<i64>(E, Sm.eps[i]);
+      Mat adj = adjugate(Ml);
+      i64 sg = dm < 0 ? -1 : 1;
+      for (int i = 0; i < 4; ++i) sd.w[i] = 0;
+      for (int i = 0; i < d; ++i) {
+        i128 c = 0;
+        for (int j = 0; j < d; ++j) c += (i128)adj.a[i][j] * v[j];
+        c *= sg;
+        // coefficient of h_i is c / m; times E must be integral
+        i128 num = c * E;
+        if (num % L.ml != 0) throw StatusError{E_STATE};
+        i64 wi = narrow(num / L.ml);
+        sd.w[i] = (int)posmod(wi, E);
+      }
+      sd.E = (int)E;
+      sd.tw = tw.table(E);
+      w->lv.push_back(L);
+      Ml = L.Nl;
+    }
+    size_t fws = w->fftM->ws_elems;
+    for (auto& L : w->lv) fws = std::max(fws, L.fftN->ws_elems);
+    // F0 (m), F1 (m/2), D2 (m/2), FFT workspace
+    w->ws_elems = (size_t)(batch * w->m) * 2 + fws;
+  } catch (const StatusError&) {
+    free_wave_plan(w);
+    throw;
+  } catch (const IntOverflow&) {
+    free_wave_plan(w);
+    throw StatusError{E_OVERFLOW};
+  } catch (const SingularMatrix&) {
+    free_wave_plan(w);
+    throw StatusError{E_SINGULAR};
+  } catch (const NotIntegral&) {
+    free_wave_plan(w);
+    throw StatusError{E_NOT_INTEGRAL};
+  }
+  return w;
+}
+
+void upload_wave_plan(WavePlan* w) {
+  upload_plan(w->fftM);
+  for (auto& L : w->lv) upload_plan(L.fftN);
+  if (!w->dtab) {
+    w->dtab = upload_blob(w->blob);
+    uintptr_t base = reinterpret_cast<uintptr_t>(w->dtab);
+    for (auto& L : w->lv) patch(L.sd.tw, base);
+  }
+}
+
+void free_wave_plan(WavePlan* w) {
+  if (!w) return;
+  free_plan(w->fftM);
+  for (auto& L : w->lv) free_plan(L.fftN);
+  if (w->dtab) (void)hipFree(w->dtab);
+  delete w;
+}
+
+void dirichlet_mask(const WavePlan* w, int level, float* out) {
+  const WaveLevel& L = w->lv[level];
+  const Mat& M = L.Ml;
+  const Mat& N = L.Nl;
+  const int d = M.d;
+  i64 DM = det(M), DN = det(N);
+  i64 m = DM < 0 ? -DM : DM, n = DN < 0 ? -DN : DN;
+  i64 sM = DM < 0 ? -1 : 1, sN = DN < 0 ? -1 : 1;
+  Mat adjM = adjugate(M), adjN = adjugate(N);
+  Mat HMt, U;
+  hnf(transpose(M), HMt, U);
+  std::vector<i64> h(d);
+  for (i64 idx = 0; idx < m; ++idx) {
+    i64 r = idx;
+    for (int i = d - 1; i >= 0; --i) {
+      h[i] = r % HMt.a[i][i];
+      r /= HMt.a[i][i];
+    }
+    // t = M^{-T} h * m  reduced into [-m/2, m/2)
+    i64 t[kMaxD], hs[kMaxD], wv[kMaxD];
+    int rM = 0;
+    for (int j = 0; j < d; ++j) {
+      i128 acc = 0;
+      for (int k = 0; k < d; ++k) acc += (i128)adjM.a[k][j] * h[k];
+      acc *= sM;
+      i128 x = acc % m;
+      if (x < 0) x += m;
+      i64 tv = (i64)x;
+      if (tv >= m - m / 2) tv -= m;  // [-floor(m/2), m - floor(m/2))
+      t[j] = tv;
+      if (2 * (i128)tv == -(i128)m) ++rM;
+    }
+    // h* = M^T t / m
+    for (int i = 0; i < d; ++i) {
+      i128 acc = 0;
+      for (int j = 0; j < d; ++j) acc += (i128)M.a[j][i] * t[j];
+      hs[i] = narrow(acc / m);
+    }
+    // w = N^{-T} h* * n = sgn(det N) adj(N)^T h*
+    bool inside = true;
+    int rN = 0;
+    for (int j = 0; j < d; ++j) {
+      i128 acc = 0;
+      for (int k = 0; k < d; ++k) acc += (i128)adjN.a[k][j] * hs[k];
+      acc *= sN;
+      wv[j] = narrow(acc);
+      i128 tw2 = 2 * (i128)(wv[j] < 0 ? -wv[j] : wv[j]);
+      if (tw2 > n) inside = false;
+      if (tw2 == n) ++rN;
+    }
+    double val = 0.0;
+    if (inside) {
+      int e = 1 + rM - rN;
+      val = (e % 2 == 0) ? std::ldexp(1.0, e / 2) : std::ldexp(std::sqrt(2.0), (e - 1) / 2);
+    }
+    out[idx] = (float)val;
+  }
+}
+
+}  // namespace lfft

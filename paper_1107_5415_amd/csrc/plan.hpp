@@ -1,0 +1,131 @@
+// Host-side plans: exact integer planning, pass schedules and device tables.
+#pragma once
+#include <array>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "device.hpp"
+#include "intmat.hpp"
+
+namespace lfft {
+
+// Status codes (mirrors include/lfft.h).
+enum Status : int {
+  OK = 0,
+  E_ARG = -1,
+  E_SINGULAR = -2,
+  E_NOT_INTEGRAL = -3,
+  E_OVERFLOW = -4,
+  E_UNSUPPORTED = -5,
+  E_HIP = -6,
+  E_NOMEM = -7,
+  E_STATE = -8,
+};
+
+struct StatusError {
+  int code;
+};
+
+using Vec4 = std::array<i64, 4>;
+
+// One side of a transform: the natural residue box of a lattice and the
+// natural element reached by a unit step along every non-trivial grid axis.
+struct Side {
+  Mat H;                    // column Hermite form (upper triangular)
+  std::vector<Vec4> unit;   // reduced natural coordinates, one per grid axis
+};
+
+struct Digit {
+  int axis;                 // non-trivial grid axis
+  i64 n;                    // digit length
+  int part;                 // 0 whole axis, 1 high digit, 2 low digit
+  i64 w_in;                 // grid-coordinate weight on the input side
+  i64 w_out;                // grid-coordinate weight on the output side
+};
+
+struct PassRange {
+  int a, b;                 // digits [a, b) are transformed
+  bool post;                // four-step twiddle after this pass
+  int post_axis;
+};
+
+// A transform on one Smith basis with a fixed sign; the first/last pass
+// have two map variants (natural or grid layout) chosen at launch.
+struct Engine {
+  int sign = -1;
+  std::vector<PassDesc> passes;
+  MapDesc in_nat{}, in_grid{}, out_nat{}, out_grid{};
+  bool has_nat_in = false, has_nat_out = false;
+};
+
+// Device table staging: offsets are encoded as (offset + 1) in pointer
+// fields and patched to device addresses after the upload.
+struct Blob {
+  std::vector<uint8_t> bytes;
+  size_t add(const void* p, size_t n);
+  template <class T>
+  const T* ref(const std::vector<T>& v) {
+    return reinterpret_cast<const T*>(add(v.data(), v.size() * sizeof(T)) + 1);
+  }
+};
+
+struct LatticePlan {
+  int d = 0;
+  Mat M;
+  i64 m = 0;
+  i64 batch = 1;
+  uint32_t flags = 0;
+  Smith Sf;                 // forward basis (largest cycle along sample key e_d)
+  Smith Si;                 // basis of M^T used by the natural->natural inverse
+  bool Sf_aligned = false, Si_aligned = false;
+  Mat HM, UM, HMT, UMT;     // Hermite forms of M and M^T
+  std::vector<i64> eps;     // non-trivial elementary divisors, ascending
+  std::vector<Digit> digits;
+  std::vector<PassRange> ranges;
+  Engine fwd, inv_nat, inv_grid;
+  Blob blob;
+  void* dtab = nullptr;     // device copy of blob
+  size_t ws_elems = 0;      // workspace (complex64 elements) per call
+};
+
+LatticePlan* build_lattice_plan(int d, const i64* M, i64 batch, uint32_t flags);
+void upload_plan(LatticePlan* p);   // allocates device tables (throws StatusError)
+void free_plan(LatticePlan* p);
+
+// Natural -> grid index maps for tests (SAMPLES: lambda = Q^{-1} g mod eps,
+// FREQS: mu = R^{-T} h mod eps, in the forward basis).
+void natural_to_grid(const LatticePlan* p, int which, i64* out);
+
+struct WaveLevel {
+  Mat Ml, Nl;
+  i64 ml = 0;
+  LatticePlan* fftN = nullptr;
+  SplitDesc sd{};
+};
+
+struct WavePlan {
+  int d = 0;
+  Mat M, J;
+  int levels = 0;
+  i64 batch = 1;
+  i64 m = 0;
+  LatticePlan* fftM = nullptr;
+  std::vector<WaveLevel> lv;
+  Blob blob;
+  void* dtab = nullptr;
+  size_t ws_elems = 0;
+};
+
+WavePlan* build_wave_plan(int d, const i64* M, const i64* J, int levels, i64 batch, uint32_t flags);
+void upload_wave_plan(WavePlan* w);
+void free_wave_plan(WavePlan* w);
+// Dirichlet scaling mask of level l in natural G(M_l^T) order (Section 6.2)
+void dirichlet_mask(const WavePlan* w, int level, float* out);
+
+// Execution (stream ordered).  bstride_in/out: batch strides in elements.
+void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid,
+                  const void* in, void* out, void* ws, long long bstride_in,
+                  long long bstride_out, hipStream_t s);
+
+}  // namespace lfft

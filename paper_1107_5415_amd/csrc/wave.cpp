@@ -1,0 +1,184 @@
+// Multi-level wavelet pyramid on the device (Section 5.3: one lattice FFT,
+// then steps 3-4 on the low-pass Fourier data of every level, and one
+// inverse FFT per channel), its inverse and both adjoints.
+//
+// Layouts (complex64, batch outermost):
+//   samples  : [B][m]  natural order of G(M)
+//   coeffs   : [B][m]  = [d2^(1) | d2^(2) | ... | d2^(L) | d1^(L)], block l in
+//              natural sample order of N_l (m_l/2 points)
+//   saved    : decompose: Fourier input of every level, [B][m_l] for
+//              l = 1..L back to back; reconstruct: (d1hat, d2hat) of every
+//              level, [B][m_l/2] twice per level.
+#include "wave.hpp"
+
+#include "kernels.hpp"
+
+namespace lfft {
+
+namespace {
+void check(hipError_t e) {
+  if (e != hipSuccess) throw StatusError{E_HIP};
+}
+
+struct Bufs {
+  float2* F0;
+  float2* F1;
+  float2* D2;
+  float2* FW;
+};
+
+Bufs carve(const WavePlan* w, void* ws) {
+  float2* base = static_cast<float2*>(ws);
+  Bufs b;
+  long long bm = w->batch * w->m;
+  b.F0 = base;
+  b.F1 = base + bm;
+  b.D2 = base + bm + bm / 2;
+  b.FW = base + 2 * bm;
+  return b;
+}
+
+long long coeff_offset(const WavePlan* w, int level) {
+  long long off = 0;
+  for (int l = 0; l < level; ++l) off += w->lv[l].ml / 2;
+  return off;
+}
+}  // namespace
+
+size_t wave_saved_elems(const WavePlan* w) {
+  size_t s = 0;
+  for (auto& L : w->lv) s += (size_t)(w->batch * L.ml);
+  return s;
+}
+
+void wave_decompose(const WavePlan* w, const float2* x, const float* const* masks, float2* coeffs,
+                    float2* saved, void* ws, hipStream_t s) {
+  Bufs b = carve(w, ws);
+  const long long B = w->batch, m = w->m;
+  const int L = w->levels;
+  // Fourier data of level l lives in `cur` with batch stride m_l
+  float2* cur = saved ? saved : b.F0;
+  exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
+  long long soff = 0;
+  for (int l = 0; l < L; ++l) {
+    const WaveLevel& V = w->lv[l];
+    const long long half = V.ml / 2;
+    float2* next;
+    if (saved && l + 1 < L) {
+      next = saved + soff + B * V.ml;
+    } else {
+      next = (cur == b.F0) ? b.F1 : b.F0;
+    }
+    check(launch_split(V.sd, B, cur, V.ml, masks[l], next, b.D2, half, s));
+    exec_lattice(V.fftN, true, false, false, b.D2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
+    soff += B * V.ml;
+    cur = next;
+  }
+  const WaveLevel& VL = w->lv[L - 1];
+  exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset(w, L), b.FW, VL.ml / 2, m, s);
+}
+
+void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* const* masks,
+                      float2* x, float2* saved, void* ws, hipStream_t s) {
+  Bufs b = carve(w, ws);
+  const long long B = w->batch, m = w->m;
+  const int L = w->levels;
+  // saved slots (d1hat, d2hat) per level, level-major
+  std::vector<long long> soff(L, 0);
+  {
+    long long o = 0;
+    for (int l = 0; l < L; ++l) {
+      soff[l] = o;
+      o += B * w->lv[l].ml;
+    }
+  }
+  const WaveLevel& VL = w->lv[L - 1];
+  // ping-pong parity chosen so that level 0 reads F1 and writes F0
+  float2* cur = saved ? saved + soff[L - 1] : (((L - 1) % 2 == 0) ? b.F1 : b.F0);
+  exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset(w, L), cur, b.FW, m, VL.ml / 2, s);
+  for (int l = L - 1; l >= 0; --l) {
+    const WaveLevel& V = w->lv[l];
+    const long long half = V.ml / 2;
+    float2* d2 = saved ? saved + soff[l] + B * half : b.D2;
+    exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), d2, b.FW, m, half, s);
+    float2* next;
+    if (l == 0) {
+      next = b.F0;
+    } else if (saved) {
+      next = saved + soff[l - 1];
+    } else {
+      next = (cur == b.F0) ? b.F1 : b.F0;
+    }
+    check(launch_unsplit(V.sd, B, cur, d2, half, masks[l], next, V.ml, s));
+    cur = next;
+  }
+  exec_lattice(w->fftM, true, false, false, cur, x, b.FW, w->lv[0].ml, m, s);
+}
+
+void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* saved,
+                             const float* const* masks, float2* gx, float* const* gmasks, void* ws,
+                             hipStream_t s) {
+  Bufs b = carve(w, ws);
+  const long long B = w->batch, m = w->m;
+  const int L = w->levels;
+  std::vector<long long> soff(L, 0);
+  {
+    long long o = 0;
+    for (int l = 0; l < L; ++l) {
+      soff[l] = o;
+      o += B * w->lv[l].ml;
+    }
+  }
+  // adjoint of the last inverse FFT is the forward FFT
+  const WaveLevel& VL = w->lv[L - 1];
+  // ping-pong parity chosen so that level 0 reads F1 and writes F0
+  float2* g1 = ((L - 1) % 2 == 0) ? b.F1 : b.F0;
+  exec_lattice(VL.fftN, false, false, false, gc + coeff_offset(w, L), g1, b.FW, m, VL.ml / 2, s);
+  for (int l = L - 1; l >= 0; --l) {
+    const WaveLevel& V = w->lv[l];
+    const long long half = V.ml / 2;
+    exec_lattice(V.fftN, false, false, false, gc + coeff_offset(w, l), b.D2, b.FW, m, half, s);
+    if (gmasks && gmasks[l] && saved)
+      check(launch_split_mask_grad(V.sd, B, saved + soff[l], V.ml, g1, b.D2, half, gmasks[l], s));
+    float2* next = (l == 0) ? b.F0 : ((g1 == b.F0) ? b.F1 : b.F0);
+    // adjoint of the split is the unsplit with the same masks
+    check(launch_unsplit(V.sd, B, g1, b.D2, half, masks[l], next, V.ml, s));
+    g1 = next;
+  }
+  exec_lattice(w->fftM, true, false, false, g1, gx, b.FW, w->lv[0].ml, m, s);
+}
+
+void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2* saved,
+                               const float* const* masks, float2* gc, float* const* gmasks,
+                               void* ws, hipStream_t s) {
+  Bufs b = carve(w, ws);
+  const long long B = w->batch, m = w->m;
+  const int L = w->levels;
+  std::vector<long long> soff(L, 0);
+  {
+    long long o = 0;
+    for (int l = 0; l < L; ++l) {
+      soff[l] = o;
+      o += B * w->lv[l].ml;
+    }
+  }
+  // adjoint of the final inverse FFT is the forward FFT
+  float2* g = b.F0;
+  exec_lattice(w->fftM, false, false, false, gx, g, b.FW, m, w->lv[0].ml, s);
+  for (int l = 0; l < L; ++l) {
+    const WaveLevel& V = w->lv[l];
+    const long long half = V.ml / 2;
+    if (gmasks && gmasks[l] && saved)
+      check(launch_unsplit_mask_grad(V.sd, B, saved + soff[l], saved + soff[l] + B * half, half, g,
+                                     V.ml, gmasks[l], s));
+    float2* next = (g == b.F0) ? b.F1 : b.F0;
+    // adjoint of the unsplit is the split with the same masks
+    check(launch_split(V.sd, B, g, V.ml, masks[l], next, b.D2, half, s));
+    exec_lattice(V.fftN, true, false, false, b.D2, gc + coeff_offset(w, l), b.FW, half, m, s);
+    g = next;
+  }
+  const WaveLevel& VL = w->lv[L - 1];
+  exec_lattice(VL.fftN, true, false, false, g, gc + coeff_offset(w, L), b.FW, VL.ml / 2, m, s);
+}
+
+}  // namespace lfft

@@ -1,0 +1,367 @@
+"""Thin Python binding of liblfft.so (argument marshalling only).
+
+Every transform runs in the library's HIP kernels; PyTorch is used for device
+memory and the current stream.  There is no fallback: if the library is not
+built, or a call fails, a RuntimeError is raised.
+
+Names follow the C ABI in include/lfft.h.
+"""
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblfft.so")
+
+LFFT_HOST_ONLY = 0x1
+LFFT_IN_NATURAL = 0x0
+LFFT_IN_GRID = 0x1
+LFFT_OUT_NATURAL = 0x0
+LFFT_OUT_GRID = 0x2
+LFFT_MAP_SAMPLES = 0
+LFFT_MAP_FREQS = 1
+LFFT_MAP_SAMPLES_T = 2
+LFFT_MAP_FREQS_T = 3
+
+EXPORTS = [
+    "lfft_plan_create", "lfft_plan_destroy", "lfft_plan_query", "lfft_plan_query_inverse_basis",
+    "lfft_plan_info", "lfft_index_map", "lfft_workspace_size", "lfft_forward", "lfft_inverse",
+    "lwt_plan_create", "lwt_plan_destroy", "lwt_level_info", "lwt_dirichlet_mask",
+    "lwt_workspace_size", "lwt_saved_elems", "lwt_decompose", "lwt_reconstruct",
+    "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_strerror",
+]
+
+_lib = None
+_lock = threading.Lock()
+
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int)
+_FP = ctypes.POINTER(ctypes.c_float)
+
+
+class LfftError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s failed: %s (status %d)" % (what, strerror(code), code))
+
+
+def lib():
+    """Load liblfft.so (raises RuntimeError if it is not built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblfft.so is not built (python -m paper_1107_5415_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "lfft_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _I64P, ctypes.c_int64, ctypes.c_uint32]),
+            "lfft_plan_destroy": (ctypes.c_int, [_P]),
+            "lfft_plan_query": (ctypes.c_int, [_P, _I64P, _I32P, _I64P, _I64P, _I64P, _I64P, _I64P]),
+            "lfft_plan_query_inverse_basis": (ctypes.c_int, [_P, _I64P, _I64P]),
+            "lfft_plan_info": (ctypes.c_int, [_P, _I32P, _I32P, _I32P]),
+            "lfft_index_map": (ctypes.c_int, [_P, ctypes.c_int, _I64P]),
+            "lfft_workspace_size": (ctypes.c_size_t, [_P]),
+            "lfft_forward": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_uint32, _P]),
+            "lfft_inverse": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_uint32, _P]),
+            "lwt_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _I64P, _I64P, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32]),
+            "lwt_plan_destroy": (ctypes.c_int, [_P]),
+            "lwt_level_info": (ctypes.c_int, [_P, ctypes.c_int, _I64P, _I64P, _I64P]),
+            "lwt_dirichlet_mask": (ctypes.c_int, [_P, ctypes.c_int, _FP]),
+            "lwt_workspace_size": (ctypes.c_size_t, [_P]),
+            "lwt_saved_elems": (ctypes.c_size_t, [_P]),
+            "lwt_decompose": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+            "lwt_reconstruct": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+            "lwt_decompose_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+            "lwt_reconstruct_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+            "lfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+        return L
+
+
+def strerror(code):
+    return lib().lfft_strerror(int(code)).decode()
+
+
+def _check(code, what):
+    if code != 0:
+        raise LfftError(code, what)
+
+
+def _mat(M):
+    M = np.asarray(M, dtype=np.int64)
+    if M.ndim != 2 or M.shape[0] != M.shape[1]:
+        raise ValueError("square integer matrix expected")
+    return np.ascontiguousarray(M)
+
+
+def _ptr64(a):
+    return a.ctypes.data_as(_I64P)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class LatticePlan:
+    """Plan of the lattice FFT on P(M) for `batch` signals (lfft_plan_*)."""
+
+    def __init__(self, M, batch=1, host_only=False):
+        self.M = _mat(M)
+        self.d = self.M.shape[0]
+        self.batch = int(batch)
+        self.host_only = bool(host_only)
+        h = _P()
+        _check(lib().lfft_plan_create(ctypes.byref(h), self.d, _ptr64(self.M), self.batch,
+                                      LFFT_HOST_ONLY if host_only else 0), "lfft_plan_create")
+        self._h = h
+        self._ws = None
+        q = self.query()
+        self.m = q["m"]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lfft_plan_destroy(h)
+            self._h = None
+
+    def query(self):
+        d = self.d
+        m = ctypes.c_int64()
+        dM = ctypes.c_int()
+        eps = np.zeros(d, np.int64)
+        Q = np.zeros((d, d), np.int64)
+        R = np.zeros((d, d), np.int64)
+        H = np.zeros((d, d), np.int64)
+        HT = np.zeros((d, d), np.int64)
+        _check(lib().lfft_plan_query(self._h, ctypes.byref(m), ctypes.byref(dM), _ptr64(eps),
+                                     _ptr64(Q), _ptr64(R), _ptr64(H), _ptr64(HT)), "lfft_plan_query")
+        Qt = np.zeros((d, d), np.int64)
+        Rt = np.zeros((d, d), np.int64)
+        _check(lib().lfft_plan_query_inverse_basis(self._h, _ptr64(Qt), _ptr64(Rt)),
+               "lfft_plan_query_inverse_basis")
+        npass = ctypes.c_int()
+        af = ctypes.c_int()
+        ai = ctypes.c_int()
+        _check(lib().lfft_plan_info(self._h, ctypes.byref(npass), ctypes.byref(af), ctypes.byref(ai)),
+               "lfft_plan_info")
+        return dict(m=m.value, d_M=dM.value, eps=eps, Q=Q, R=R, H_M=H, H_MT=HT, Qt=Qt, Rt=Rt,
+                    passes=npass.value, aligned_forward=bool(af.value), aligned_inverse=bool(ai.value))
+
+    def index_map(self, which):
+        out = np.zeros(self.m, np.int64)
+        _check(lib().lfft_index_map(self._h, int(which), _ptr64(out)), "lfft_index_map")
+        return out
+
+    def workspace_bytes(self):
+        return int(lib().lfft_workspace_size(self._h))
+
+    def _workspace(self, device):
+        torch = _torch()
+        nb = self.workspace_bytes()
+        if nb == 0:
+            return None
+        if self._ws is None or self._ws.device != device:
+            self._ws = torch.empty(nb // 8, dtype=torch.complex64, device=device)
+        return self._ws
+
+    def _run(self, fn, x, out, layout, what):
+        torch = _torch()
+        if not x.is_cuda:
+            raise RuntimeError("lattice FFT input must be a HIP device tensor")
+        if x.dtype != torch.complex64:
+            raise RuntimeError("complex64 expected")
+        x = x.contiguous()
+        if x.numel() != self.batch * self.m:
+            raise RuntimeError("expected %d elements, got %d" % (self.batch * self.m, x.numel()))
+        if out is None:
+            out = torch.empty_like(x)
+        ws = self._workspace(x.device)
+        _check(fn(self._h, _dptr(x), _dptr(out), _dptr(ws) if ws is not None else None,
+                  int(layout), _stream_handle(x.device)), what)
+        return out
+
+    def forward(self, x, out=None, layout=0):
+        return self._run(lib().lfft_forward, x, out, layout, "lfft_forward")
+
+    def inverse(self, x, out=None, layout=0):
+        return self._run(lib().lfft_inverse, x, out, layout, "lfft_inverse")
+
+
+_plan_cache = {}
+
+
+def get_plan(M, batch=1):
+    key = (tuple(map(tuple, _mat(M).tolist())), int(batch))
+    p = _plan_cache.get(key)
+    if p is None:
+        p = LatticePlan(M, batch)
+        _plan_cache[key] = p
+    return p
+
+
+def forward(x, M):
+    """Unitary lattice DFT of x (complex64 [..., m], natural sample order)."""
+    m = x.shape[-1]
+    b = x.numel() // m
+    return get_plan(M, b).forward(x).reshape(x.shape)
+
+
+def inverse(x, M):
+    m = x.shape[-1]
+    b = x.numel() // m
+    return get_plan(M, b).inverse(x).reshape(x.shape)
+
+
+class WaveletPlan:
+    """Plan of the multi-level lattice wavelet pyramid (lwt_plan_*)."""
+
+    def __init__(self, M, J, levels, batch=1, host_only=False):
+        self.M = _mat(M)
+        self.J = _mat(J)
+        self.d = self.M.shape[0]
+        self.levels = int(levels)
+        self.batch = int(batch)
+        h = _P()
+        _check(lib().lwt_plan_create(ctypes.byref(h), self.d, _ptr64(self.M), _ptr64(self.J),
+                                     self.levels, self.batch, LFFT_HOST_ONLY if host_only else 0),
+               "lwt_plan_create")
+        self._h = h
+        self._ws = None
+        self.level_m = []
+        self.level_N = []
+        for l in range(self.levels):
+            N = np.zeros((self.d, self.d), np.int64)
+            ml = ctypes.c_int64()
+            eps = np.zeros(self.d, np.int64)
+            _check(lib().lwt_level_info(self._h, l, _ptr64(N), ctypes.byref(ml), _ptr64(eps)),
+                   "lwt_level_info")
+            self.level_m.append(ml.value)
+            self.level_N.append(N)
+        self.m = self.level_m[0]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lwt_plan_destroy(h)
+            self._h = None
+
+    def dirichlet_mask(self, level):
+        out = np.zeros(self.level_m[level], np.float32)
+        _check(lib().lwt_dirichlet_mask(self._h, int(level), out.ctypes.data_as(_FP)),
+               "lwt_dirichlet_mask")
+        return out
+
+    def dirichlet_masks(self, device=None):
+        torch = _torch()
+        ms = [self.dirichlet_mask(l) for l in range(self.levels)]
+        if device is None:
+            return ms
+        return [torch.from_numpy(a).to(device) for a in ms]
+
+    def saved_elems(self):
+        return int(lib().lwt_saved_elems(self._h))
+
+    def _workspace(self, device):
+        torch = _torch()
+        nb = int(lib().lwt_workspace_size(self._h))
+        if self._ws is None or self._ws.device != device:
+            self._ws = torch.empty(max(nb // 8, 1), dtype=torch.complex64, device=device)
+        return self._ws
+
+    def _masks(self, masks):
+        torch = _torch()
+        if len(masks) != self.levels:
+            raise RuntimeError("one mask per level expected")
+        ms = []
+        for l, mk in enumerate(masks):
+            if mk.dtype != torch.float32 or not mk.is_cuda or mk.numel() != self.level_m[l]:
+                raise RuntimeError("mask %d must be a float32 device tensor of %d elements" % (l, self.level_m[l]))
+            ms.append(mk.contiguous())
+        arr = (ctypes.c_void_p * self.levels)(*[m.data_ptr() for m in ms])
+        return ms, arr
+
+    def _grad_masks(self, gmasks):
+        if gmasks is None:
+            return None
+        return (ctypes.c_void_p * self.levels)(*[g.data_ptr() for g in gmasks])
+
+    def _check_signal(self, x):
+        torch = _torch()
+        if not x.is_cuda or x.dtype != torch.complex64 or x.numel() != self.batch * self.m:
+            raise RuntimeError("complex64 device tensor of %d elements expected" % (self.batch * self.m))
+        return x.contiguous()
+
+    def new_saved(self, device):
+        torch = _torch()
+        return torch.empty(self.saved_elems(), dtype=torch.complex64, device=device)
+
+    def decompose(self, x, masks, saved=None, out=None):
+        torch = _torch()
+        x = self._check_signal(x)
+        ms, arr = self._masks(masks)
+        if out is None:
+            out = torch.empty_like(x)
+        ws = self._workspace(x.device)
+        _check(lib().lwt_decompose(self._h, _dptr(x), ctypes.cast(arr, _P), _dptr(out),
+                                   _dptr(saved) if saved is not None else None, _dptr(ws),
+                                   _stream_handle(x.device)), "lwt_decompose")
+        return out
+
+    def reconstruct(self, c, masks, saved=None, out=None):
+        torch = _torch()
+        c = self._check_signal(c)
+        ms, arr = self._masks(masks)
+        if out is None:
+            out = torch.empty_like(c)
+        ws = self._workspace(c.device)
+        _check(lib().lwt_reconstruct(self._h, _dptr(c), ctypes.cast(arr, _P), _dptr(out),
+                                     _dptr(saved) if saved is not None else None, _dptr(ws),
+                                     _stream_handle(c.device)), "lwt_reconstruct")
+        return out
+
+    def decompose_backward(self, grad_c, saved, masks, grad_masks=None):
+        torch = _torch()
+        g = self._check_signal(grad_c)
+        ms, arr = self._masks(masks)
+        gx = torch.empty_like(g)
+        gm = self._grad_masks(grad_masks)
+        ws = self._workspace(g.device)
+        _check(lib().lwt_decompose_backward(self._h, _dptr(g), _dptr(saved) if saved is not None else None,
+                                            ctypes.cast(arr, _P), _dptr(gx),
+                                            ctypes.cast(gm, _P) if gm is not None else None,
+                                            _dptr(ws), _stream_handle(g.device)),
+               "lwt_decompose_backward")
+        return gx
+
+    def reconstruct_backward(self, grad_x, saved, masks, grad_masks=None):
+        torch = _torch()
+        g = self._check_signal(grad_x)
+        ms, arr = self._masks(masks)
+        gc = torch.empty_like(g)
+        gm = self._grad_masks(grad_masks)
+        ws = self._workspace(g.device)
+        _check(lib().lwt_reconstruct_backward(self._h, _dptr(g), _dptr(saved) if saved is not None else None,
+                                              ctypes.cast(arr, _P), _dptr(gc),
+                                              ctypes.cast(gm, _P) if gm is not None else None,
+                                              _dptr(ws), _stream_handle(g.device)),
+               "lwt_reconstruct_backward")
+        return gc

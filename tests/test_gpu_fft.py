@@ -1,0 +1,170 @@
+"""GPU parity of the lattice FFT (C ABI through the binding) against the FP64
+oracle: element-wise relative L2 <= 1e-5 in FP32 (tolerance of the
+plain-FP32 path), on seeded inputs."""
+import numpy as np
+import pytest
+
+from oracle import dft, lattice as L
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _lfft():
+    from paper_1107_5415_amd import lfft
+    return lfft
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_fft(M, x, inverse=False):
+    m = abs(L.det(M))
+    x = np.asarray(x, np.complex128)
+    if m <= 2048:
+        return dft.lattice_dft_direct(M, x, inverse=inverse)
+    return dft.lattice_dft_hnf(M, x, inverse=inverse)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+CASES = [
+    ("small_1088_radix17", ((32, 8), (-8, 32)), 3),
+    ("example1_cyclic32", ((4, -3), (4, 5)), 2),
+    ("odd_primes", ((3 * 5, 4), (0, 7 * 11)), 2),
+    ("generic_prime_23", ((23, 5), (0, 46)), 1),
+    ("negative_det", ((-7, 2), (3, 5)), 4),
+    ("d3_small", ((3, 1, 0), (0, 3, 1), (1, 0, 3)), 2),
+    ("d3_mixed", ((6, 0, 0), (0, 10, 0), (0, 0, 15)), 1),
+    ("d4_small", ((2, 1, 0, 0), (0, 3, 1, 0), (1, 0, 4, 1), (0, 1, 0, 5)), 1),
+    ("two_pass_2^14", ((128, 32), (0, 128)), 2),
+    ("two_pass_odd", ((105, 0), (0, 1287)), 1),
+    ("split_then_axis_d3", ((16, 0, 0), (0, 1024, 3), (0, 0, 1024)), 1),
+    ("three_axes_three_pass", ((16, 0, 0), (0, 1024, 0), (0, 0, 1024)), 1),
+    ("split_axis_2^18", ((1, 0), (0, 1 << 18)), 1),
+    ("split_axis_plus_axis", ((2, 0), (0, 1 << 17)), 2),
+    ("quincunx_level", ((2048, 3072), (2048, -1024)), 1),
+    ("tile_ragged", ((7, 3), (0, 9)), 5),
+    ("trivial_m1", ((1, 0), (0, 1)), 3),
+]
+
+
+@pytest.mark.parametrize("name,M,batch", CASES, ids=[c[0] for c in CASES])
+def test_forward_inverse_natural(name, M, batch):
+    lfft = _lfft()
+    m = abs(L.det(M))
+    print("case", name, "m", m, "batch", batch, flush=True)
+    x = workloads.complex_normal(11, (batch, m))
+    plan = lfft.LatticePlan(M, batch=batch)
+    X = plan.forward(_dev(x)).cpu().numpy()
+    ref = oracle_fft(M, x)
+    assert rel_l2(X, ref) < TOL
+    z = workloads.complex_normal(12, (batch, m))
+    Z = plan.inverse(_dev(z)).cpu().numpy()
+    assert rel_l2(Z, oracle_fft(M, z, inverse=True)) < TOL
+
+
+def _maps_from_oracle(M, q):
+    """natural->grid maps recomputed from the plan's (Q, R) with exact ints."""
+    d = len(M)
+    eps = [int(e) for e in q["eps"]]
+    nz = [j for j in range(d) if eps[j] > 1]
+    Q = tuple(map(tuple, q["Q"].tolist()))
+    R = tuple(map(tuple, q["R"].tolist()))
+    Qinv = np.array(L.inverse(Q), dtype=object).astype(np.int64)
+    RinvT = np.array(L.transpose(L.inverse(R)), dtype=object).astype(np.int64)
+    g = dft.natural_keys(M, "samples")
+    h = dft.natural_keys(M, "freqs")
+
+    def lin(keys, A):
+        v = keys @ A.T
+        out = np.zeros(keys.shape[0], np.int64)
+        for j in nz:
+            out = out * eps[j] + np.mod(v[:, j], eps[j])
+        return out
+    return lin(g, Qinv), lin(h, RinvT)
+
+
+@pytest.mark.parametrize("M", [((32, 8), (-8, 32)), ((128, 32), (0, 128)), ((2, 0), (0, 1 << 17)),
+                               ((3, 1, 0), (0, 3, 1), (1, 0, 3))])
+def test_grid_layouts(M):
+    """GRID order (Theorem 1, no rearrangement): every in/out layout pair."""
+    lfft = _lfft()
+    m = abs(L.det(M))
+    plan = lfft.LatticePlan(M, batch=2)
+    smap, fmap = _maps_from_oracle(M, plan.query())
+    x = workloads.complex_normal(13, (2, m))
+    ref = oracle_fft(M, x)
+    xg = np.empty_like(x)
+    xg[:, smap] = x
+    refg = np.empty_like(ref)
+    refg[:, fmap] = ref
+    for lay, src, want in [(lfft.LFFT_IN_GRID, xg, ref), (lfft.LFFT_OUT_GRID, x, refg),
+                           (lfft.LFFT_IN_GRID | lfft.LFFT_OUT_GRID, xg, refg)]:
+        out = plan.forward(_dev(src), layout=lay).cpu().numpy()
+        assert rel_l2(out, want) < TOL, lay
+    # inverse in grid layouts
+    z = workloads.complex_normal(14, (2, m))
+    zref = oracle_fft(M, z, inverse=True)
+    zg = np.empty_like(z)
+    zg[:, fmap] = z
+    zrefg = np.empty_like(zref)
+    zrefg[:, smap] = zref
+    for lay, src, want in [(lfft.LFFT_IN_GRID, zg, zref), (lfft.LFFT_OUT_GRID, z, zrefg),
+                           (lfft.LFFT_IN_GRID | lfft.LFFT_OUT_GRID, zg, zrefg)]:
+        out = plan.inverse(_dev(src), layout=lay).cpu().numpy()
+        assert rel_l2(out, want) < TOL, lay
+
+
+def test_large_forward_inverse_full_size():
+    """d = 2, M = [[4096, 2048], [0, 4096]], m = 2^24 in the launch
+    configuration the benchmark times; checked against the Hermite-form FP64
+    FFT (an independent algorithm) and against exact direct bins."""
+    lfft = _lfft()
+    cfg = workloads.CONFIGS["large"]
+    M = cfg["M"]
+    m = 1 << 24
+    x = workloads.complex_normal(cfg["seed"], m)
+    plan = lfft.LatticePlan(M, batch=1)
+    X = plan.forward(_dev(x)).cpu().numpy()
+    ref = dft.lattice_dft_hnf(M, x)
+    assert rel_l2(X, ref) < TOL
+    HT, _ = L.hnf(L.transpose(M))
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, m, 16)
+    hs = [tuple(int(v) for v in dft.natural_keys(M, "freqs")[i]) for i in idx[:4]]
+    bins = dft.direct_bins(M, x, hs)
+    np.testing.assert_allclose(X[idx[:4]], bins, rtol=0, atol=2e-5 * np.abs(bins).max() + 1e-4)
+    z = workloads.complex_normal(cfg["seed"] + 100, m)
+    Z = plan.inverse(_dev(z)).cpu().numpy()
+    assert rel_l2(Z, dft.lattice_dft_hnf(M, z, inverse=True)) < TOL
+
+
+def test_d3_full_size_forward():
+    lfft = _lfft()
+    cfg = workloads.CONFIGS["d3"]
+    M = cfg["M"]
+    x = workloads.complex_normal(cfg["seed"], 1 << 24)
+    X = lfft.LatticePlan(M).forward(_dev(x)).cpu().numpy()
+    assert rel_l2(X, dft.lattice_dft_hnf(M, x)) < TOL
+
+
+def test_properties_at_any_size():
+    """Unitarity and inverse(forward) = id on the large workload."""
+    lfft = _lfft()
+    M = workloads.CONFIGS["large"]["M"]
+    x = _dev(workloads.complex_normal(21, 1 << 24))
+    plan = lfft.LatticePlan(M)
+    X = plan.forward(x)
+    nx = torch.linalg.vector_norm(x.to(torch.complex128)).item()
+    nX = torch.linalg.vector_norm(X.to(torch.complex128)).item()
+    assert abs(nX / nx - 1) < 1e-5
+    back = plan.inverse(X)
+    err = torch.linalg.vector_norm((back - x).to(torch.complex128)).item() / nx
+    assert err < 2e-5

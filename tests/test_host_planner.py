@@ -1,0 +1,206 @@
+"""CPU tests of the C-ABI host planner (integer work only, no GPU): every
+exported integer object is compared bit-exactly with the oracle's
+independent recomputation."""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import lattice as L, wavelet as W
+import workloads
+
+lfft = pytest.importorskip("paper_1107_5415_amd.lfft")
+LIB_OK = os.path.exists(lfft.LIB_PATH)
+pytestmark = pytest.mark.skipif(not LIB_OK, reason="liblfft.so not built")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_match_header():
+    """The library loads and exports every function include/lfft.h declares."""
+    hdr = open(os.path.join(ROOT, "include", "lfft.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(l(?:fft|wt)_\w+)\(", hdr, re.M))
+    assert declared == set(lfft.EXPORTS)
+    L_ = ctypes.CDLL(lfft.LIB_PATH)
+    for name in declared:
+        assert hasattr(L_, name), name
+
+
+MATS = [
+    ((32, 8), (-8, 32)),
+    ((4096, 2048), (0, 4096)),
+    ((256, 64, 0), (0, 256, 64), (0, 0, 256)),
+    ((1024, 256), (0, 1024)),
+    ((4, -3), (4, 5)),
+    ((5, 2), (1, 3)),
+    ((3, 1, 0), (0, 3, 1), (1, 0, 3)),
+    ((-7, 2), (3, 5)),
+    ((12, 4), (0, 6)),
+    ((6, 0, 0), (0, 10, 0), (0, 0, 15)),
+    ((2, 1, 0, 0), (0, 3, 1, 0), (1, 0, 4, 1), (0, 1, 0, 5)),
+    ((1, 0), (0, 1 << 18)),
+    ((8, 0), (0, 8)),
+] + [workloads.table1_matrix(i) for i in (1, 2, 0, 1024)]
+
+
+def _mat_np(M):
+    return np.array(M, dtype=object)
+
+
+@pytest.mark.parametrize("M", MATS)
+def test_plan_integer_data(M):
+    p = lfft.LatticePlan(M, host_only=True)
+    q = p.query()
+    d = len(M)
+    eps = tuple(int(x) for x in q["eps"])
+    assert eps == L.elementary_divisors(M)
+    assert q["m"] == abs(L.det(M))
+    assert q["d_M"] == L.pattern_dimension(M)
+    assert tuple(map(tuple, q["H_M"].tolist())) == L.hnf(M)[0]
+    assert tuple(map(tuple, q["H_MT"].tolist())) == L.hnf(L.transpose(M))[0]
+    E = tuple(tuple(eps[i] if i == j else 0 for j in range(d)) for i in range(d))
+    Q = tuple(map(tuple, q["Q"].tolist()))
+    R = tuple(map(tuple, q["R"].tolist()))
+    assert L.matmul(L.matmul(Q, E), R) == tuple(map(tuple, M))
+    assert abs(L.det(Q)) == 1 and abs(L.det(R)) == 1
+    Qt = tuple(map(tuple, q["Qt"].tolist()))
+    Rt = tuple(map(tuple, q["Rt"].tolist()))
+    assert L.matmul(L.matmul(Qt, E), Rt) == L.transpose(M)
+    assert abs(L.det(Qt)) == 1 and abs(L.det(Rt)) == 1
+
+
+def _grid_coords(lin, eps):
+    nz = [e for e in eps if e > 1]
+    out = []
+    for e in reversed(nz):
+        out.append(lin % e)
+        lin //= e
+    return list(reversed(out))
+
+
+@pytest.mark.parametrize("M", [M for M in MATS if abs(L.det(M)) <= 4096])
+def test_index_maps_exact(M):
+    """natural->grid maps equal lambda = Q^{-1} g mod eps and mu = R^{-T} h mod
+    eps recomputed with exact rationals from the plan's (Q, R); they are
+    bijections; and the phase identity of Lemma 1 / Theorem 1 holds for every
+    pair: h^T M^{-1} g = sum_j mu_j lambda_j / eps_j (mod 1)."""
+    p = lfft.LatticePlan(M, host_only=True)
+    q = p.query()
+    d = len(M)
+    m = q["m"]
+    eps = [int(x) for x in q["eps"]]
+    nz = [j for j in range(d) if eps[j] > 1]
+    for which, (Qn, Rn, A) in enumerate([("Q", "R", M), ("Qt", "Rt", L.transpose(M))]):
+        Q = tuple(map(tuple, q[Qn].tolist()))
+        R = tuple(map(tuple, q[Rn].tolist()))
+        Qinv = L.inverse(Q)
+        RinvT = L.transpose(L.inverse(R))
+        HA, _ = L.hnf(A)
+        HAT, _ = L.hnf(L.transpose(A))
+        smap = p.index_map(2 * which)
+        fmap = p.index_map(2 * which + 1)
+        assert np.array_equal(np.sort(smap), np.arange(m))
+        assert np.array_equal(np.sort(fmap), np.arange(m))
+        gs = L.box_points(HA)
+        hs = L.box_points(HAT)
+        lam = []
+        for i, g in enumerate(gs):
+            v = L.matvec(Qinv, g)
+            c = [int(v[j]) % eps[j] for j in nz]
+            assert all(x.denominator == 1 for x in v)
+            lin = 0
+            for j, cj in zip(nz, c):
+                lin = lin * eps[j] + cj
+            assert smap[i] == lin
+            lam.append(c)
+        mu = []
+        for i, h in enumerate(hs):
+            v = L.matvec(RinvT, h)
+            c = [int(v[j]) % eps[j] for j in nz]
+            lin = 0
+            for j, cj in zip(nz, c):
+                lin = lin * eps[j] + cj
+            assert fmap[i] == lin
+            mu.append(c)
+        # phase identity on a sample of pairs (all pairs when small)
+        rng = np.random.default_rng(0)
+        pairs = [(a, b) for a in range(m) for b in range(m)] if m <= 256 else \
+            [(int(rng.integers(m)), int(rng.integers(m))) for _ in range(4000)]
+        for ih, ig in pairs:
+            r = L.phase_residue(A, hs[ih], gs[ig])
+            s = sum(Fraction(mu[ih][t] * lam[ig][t], eps[nz[t]]) for t in range(len(nz)))
+            assert (Fraction(r, m) - s).denominator == 1
+
+
+def test_forward_basis_aligned_for_workloads():
+    """The chosen basis puts the largest cycle along the last natural sample
+    coordinate (Remark 1), so the first pass reads contiguous rows."""
+    for name in ("small", "large", "d3", "grad"):
+        p = lfft.LatticePlan(workloads.CONFIGS[name]["M"], host_only=True)
+        assert p.query()["aligned_forward"]
+
+
+@pytest.mark.parametrize("M,J,levels", [
+    (((32, 8), (-8, 32)), workloads.J_QUINCUNX, 1),
+    (((16, 8), (0, 16)), workloads.J_QUINCUNX, 4),
+    (((8, 0), (0, 8)), workloads.J_X, 3),
+    (((12, 4), (0, 6)), workloads.J_X, 1),
+    (((6, 2, 0), (0, 4, 2), (0, 0, 6)), ((2, 0, 0), (0, 1, 0), (0, 0, 1)), 1),
+])
+def test_wavelet_levels_and_masks(M, J, levels):
+    w = lfft.WaveletPlan(M, J, levels, host_only=True)
+    mats = W.level_matrices(M, J, levels)
+    for l, (Ml, Nl) in enumerate(mats):
+        assert tuple(map(tuple, w.level_N[l].tolist())) == Nl
+        assert w.level_m[l] == abs(L.det(Ml))
+        ref = W.dirichlet_mask(Ml, Nl)
+        got = w.dirichlet_mask(l).astype(np.float64)
+        # exact categories; values exactly float32(sqrt 2), 1 or 0
+        assert np.array_equal(got, ref.astype(np.float32).astype(np.float64))
+        assert set(np.unique(got)) <= {0.0, 1.0, float(np.float32(np.sqrt(2.0)))}
+
+
+def test_wavelet_masks_large_level_chain():
+    M = workloads.CONFIGS["grad"]["M"]
+    w = lfft.WaveletPlan(M, workloads.J_QUINCUNX, 4, host_only=True)
+    for l, (Ml, Nl) in enumerate(W.level_matrices(M, workloads.J_QUINCUNX, 4)):
+        ref = W.dirichlet_mask(Ml, Nl).astype(np.float32)
+        assert np.array_equal(w.dirichlet_mask(l), ref)
+
+
+def _err(fn):
+    with pytest.raises(lfft.LfftError) as e:
+        fn()
+    return e.value.code
+
+
+def test_error_codes():
+    assert _err(lambda: lfft.LatticePlan([[1, 2], [2, 4]], host_only=True)) == -2        # singular
+    assert _err(lambda: lfft.LatticePlan(np.eye(5, dtype=int), host_only=True)) == -5    # d > 4
+    assert _err(lambda: lfft.LatticePlan([[1 << 40, 0], [0, 1 << 40]], host_only=True)) in (-4, -5)
+    assert _err(lambda: lfft.LatticePlan([[(1 << 62), 1], [1, (1 << 62)]], host_only=True)) == -4
+    assert _err(lambda: lfft.LatticePlan([[4, 0], [0, 4]], batch=0, host_only=True)) == -1
+    # J^{-1} M not integral: quincunx needs rows of equal parity
+    assert _err(lambda: lfft.WaveletPlan([[3, 0], [0, 4]], workloads.J_QUINCUNX, 1, host_only=True)) == -3
+    # |det J| != 2
+    assert _err(lambda: lfft.WaveletPlan([[8, 0], [0, 8]], [[2, 0], [0, 2]], 1, host_only=True)) == -5
+    # integral first level, non-integral later level
+    assert _err(lambda: lfft.WaveletPlan([[4, 0], [0, 2]], workloads.J_X, 3, host_only=True)) == -3
+    # a large prime cycle cannot be split to fit on chip
+    assert _err(lambda: lfft.LatticePlan([[1, 0], [0, 8209 * 2]], host_only=True)) == -5
+    # execute on a host-only plan
+    p = lfft.LatticePlan([[4, 0], [0, 4]], host_only=True)
+    lib = lfft.lib()
+    buf = (ctypes.c_float * 64)()
+    buf2 = (ctypes.c_float * 64)()
+    assert lib.lfft_forward(p._h, ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf2, ctypes.c_void_p),
+                            None, 0, None) == -8
+    assert lib.lfft_forward(p._h, ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf, ctypes.c_void_p),
+                            None, 0, None) == -1
+    assert lib.lfft_forward(None, None, None, None, 0, None) == -1
+    assert lib.lfft_forward(p._h, ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf2, ctypes.c_void_p),
+                            None, 0x10, None) == -1
+    assert lfft.strerror(-3).startswith("J^{-1} M")
