@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice FFT + fast lattice wavelet decomposition hot path.
+
+Workload (one "step" = one pass of the whole hot path over one signal):
+  d = 2, M = [[4096, 2048], [0, 4096]], m = 2^24 points, complex64 samples
+  (i.i.d. complex N(0,1), seed 2), J = [[1, 1], [1, -1]] (quincunx),
+  8 levels with Dirichlet masks:
+    forward lattice FFT, inverse lattice FFT, 8-level decomposition
+    (FFT on M, 8 splits, 9 channel inverse FFTs) and its reconstruction.
+Inputs are resident in HBM before the timed region.
+
+value = lattice-FFT GFLOP/s over the step: sum over every lattice FFT the
+step executes of 5 m_i log2 m_i, divided by the step time (the splits add
+time but no flops).  The forward FFT alone is reported beside it.
+
+Prints ONE JSON line on stdout (progress goes to stderr).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+WORKLOAD = "large"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fft_flops(m):
+    return 5.0 * m * math.log2(m) if m > 1 else 0.0
+
+
+def step_flops(m, levels):
+    """5 m log2 m summed over every lattice FFT of one step."""
+    ms = [m >> l for l in range(levels)]          # m_l of the levels
+    halves = [ml // 2 for ml in ms]
+    f = fft_flops(m) * 2                          # forward + inverse
+    f += fft_flops(m) + sum(fft_flops(h) for h in halves) + fft_flops(halves[-1])   # decompose
+    f += fft_flops(halves[-1]) + sum(fft_flops(h) for h in halves) + fft_flops(m)   # reconstruct
+    return f
+
+
+def source_digest(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1107_5415_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM traffic per launch from committed rocprofv3 counter runs, or None
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    ent = t.get(kernel)
+    if not ent:
+        return None
+    if ent.get("source_digest") != source_digest(ent.get("sources", [])):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, m, levels):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload: the forward lattice FFT and the 8-level decomposition of the
+    m = 2^24 signal (about half of one step)."""
+    import numpy as np
+    import workloads
+    from oracle import dft, wavelet
+    M, J = cfg["M"], cfg["J"]
+    x = workloads.complex_normal(cfg["seed"], m).astype(np.complex128)
+    t0 = time.perf_counter()
+    dft.lattice_dft_hnf(M, x)
+    wavelet.decompose(x, M, J, levels)
+    dt = time.perf_counter() - t0
+    halves = [(m >> l) // 2 for l in range(levels)]
+    flops = 2 * fft_flops(m) + sum(fft_flops(h) for h in halves) + fft_flops(halves[-1])
+    return dict(value=round(flops / dt / 1e9, 4), unit="GFLOP/s", cores=os.cpu_count(),
+                kind="oracle",
+                sample="forward lattice FFT + 8-level decomposition of the m = 2^24 signal in "
+                       "float64 (Hermite row/column FFT, scipy.fft workers=%d): %.1f s"
+                       % (os.cpu_count(), dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the lattice FFT/wavelet hot path runs on a single "
+              "MI355X here (multi-GPU sharding is design-only); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1107_5415_amd import lfft
+
+    cfg = workloads.CONFIGS[WORKLOAD]
+    M, J, levels = cfg["M"], cfg["J"], cfg["levels"]
+    dev = torch.device("cuda:0")
+    m = 1 << 24
+    log("bench: building plans")
+    fplan = lfft.LatticePlan(M)
+    wplan = lfft.WaveletPlan(M, J, levels)
+    masks = wplan.dirichlet_masks(dev)
+    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], m)).to(dev)
+    X = torch.empty_like(x)
+    Y = torch.empty_like(x)
+    C = torch.empty_like(x)
+    Rr = torch.empty_like(x)
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        fplan.forward(x, out=X)
+        if ev:
+            ev[1].record()
+        fplan.inverse(X, out=Y)
+        if ev:
+            ev[2].record()
+        wplan.decompose(x, masks, out=C)
+        if ev:
+            ev[3].record()
+        wplan.reconstruct(C, masks, out=Rr)
+        if ev:
+            ev[4].record()
+
+    log("bench: warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    lfft.trace_begin(100000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    trace = lfft.trace_end()
+    log("bench: timed %d steps in %.3f s" % (args.steps, t1 - t0))
+
+    ms_step = sum(evs[k][0].elapsed_time(evs[k][4]) for k in range(args.steps)) / args.steps
+    phase = {}
+    for i, name in enumerate(["fft_forward", "fft_inverse", "decompose", "reconstruct"]):
+        phase[name] = sum(evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)) / args.steps
+    flops = step_flops(m, levels)
+    value = flops / (ms_step / 1e3) / 1e9
+
+    # dominant kernel: largest total time in the traced region
+    agg = {}
+    for name, b, ms in trace:
+        a = agg.setdefault(name, [0.0, 0.0, 0])
+        a[0] += ms
+        a[1] += b
+        a[2] += 1
+    dom = max(agg, key=lambda k: agg[k][0])
+    tot_ms, tot_b, cnt = agg[dom]
+    achieved = tot_b / (tot_ms / 1e3) / 1e9
+    traffic = load_traffic(dom)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic, kernel=dom,
+                launches_per_step=cnt // args.steps,
+                avg_launch_us=round(tot_ms / cnt * 1e3, 2),
+                alg_bytes_per_launch=tot_b / cnt)
+    kernels = {k: dict(launches=v[2] // args.steps, ms_per_step=round(v[0] / args.steps, 4),
+                       gbs=round(v[1] / (v[0] / 1e3) / 1e9, 1)) for k, v in agg.items()}
+
+    fwd_ms = phase["fft_forward"]
+    out = {
+        "metric": "lattice FFT GFLOP/s (5·m·log2 m) + % HBM peak at m=2^24 vs plain FP32",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "d=2 M=[[4096,2048],[0,4096]] m=2^24 complex64 N(0,1) seed 2: "
+                               "forward+inverse lattice FFT, 8-level quincunx J=[[1,1],[1,-1]] "
+                               "Dirichlet decomposition + reconstruction",
+                   "m": m, "levels": levels, "batch": 1, "layout": "natural"},
+        "roofline": roof,
+        "fft_forward": {"ms": round(fwd_ms, 4), "gflops": round(fft_flops(m) / (fwd_ms / 1e3) / 1e9, 1),
+                        "alg_hbm_frac": round(16.0 * m / (fwd_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "phases_ms": {k: round(v, 4) for k, v in phase.items()},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host (one step)")
+        out["cpu_baseline"] = cpu_baseline(cfg, m, levels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,20 @@ int lwt_reconstruct_backward(lwt_plan_t plan, const void* grad_samples, const vo
                              const float* const* masks, void* grad_coeffs,
                              float* const* grad_masks, void* workspace, hipStream_t stream);
 
+/* ---- per-launch kernel timing (tracing) -------------------------------- */
+
+/* Start recording every kernel this library launches from now on (process
+ * wide): two HIP events on the launch stream around each launch, the kernel
+ * name and the algorithmic bytes of the launch (bytes the operation must move
+ * at minimum: 16 per complex point of an FFT pass, 20 per point of a split
+ * level).  capacity: maximum number of launches kept. */
+int lfft_trace_begin(int capacity);
+/* Stop recording; *count receives the number of recorded launches. */
+int lfft_trace_end(int* count);
+/* Launch i of the last trace: kernel name (static string), algorithmic
+ * bytes and duration in ms (waits for the launch to complete). */
+int lfft_trace_get(int i, const char** name, double* bytes, float* ms);
+
 /* Static description of a status code. */
 const char* lfft_strerror(int status);
 

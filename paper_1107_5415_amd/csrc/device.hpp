@@ -37,9 +37,15 @@ struct StageDesc {
   int stride;
   int Ns;
   const float2* tw;
+  // base-2 logarithms (power-of-two stages only, used by the fast kernel)
+  int lg_r, lg_n, lg_stride, lg_Ns;
 };
 
 struct PassDesc {
+  int kind;                   // 0 generic kernel, 1 register-resident power-of-two kernel
+  int P;                      // fast kernel: points per thread (16 or 32)
+  int W;                      // fast kernel: pencils per workgroup
+  int split;                  // fast kernel: exchange real and imaginary parts separately
   long long batch;            // number of signals
   int O, L, S;                // per-signal outer count, pencil length, inner count
   int TP;                     // pencils per tile

@@ -10,6 +10,11 @@ namespace lfft {
 // One FFT pass (gather -> Stockham stages -> optional four-step twiddle ->
 // scatter) over every tile of the batch.
 hipError_t launch_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s);
+// Name of the kernel launch_pass uses for this descriptor (for tracing).
+const char* pass_kernel_name(const PassDesc& p);
+// Register-resident power-of-two pass (descriptor kind 1).
+hipError_t launch_fast_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s);
+const char* fast_kernel_name(const PassDesc& p);
 
 // Fourier-domain wavelet split of one level (Section 5.3, step 4).
 hipError_t launch_split(const SplitDesc& sd, long long batch, const float2* ahat, long long ah_bs,

@@ -13,6 +13,7 @@
 #include <map>
 
 #include "kernels.hpp"
+#include "ktrace.hpp"
 
 namespace lfft {
 
@@ -103,6 +104,25 @@ std::vector<int> radices_of(i64 n) {
       n = 1;
     }
   }
+  return r;
+}
+
+bool is_pow2(i64 n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int ilog2(i64 n) {
+  int l = 0;
+  while ((i64(1) << l) < n) ++l;
+  return l;
+}
+
+// power-of-two digit as radices of at most 16, largest first
+std::vector<int> pow2_radices(i64 n) {
+  std::vector<int> r;
+  while (n >= 16) {
+    r.push_back(16);
+    n /= 16;
+  }
+  if (n > 1) r.push_back((int)n);
   return r;
 }
 
@@ -239,11 +259,30 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
       while (pd.S % tp) --tp;
     }
     pd.TP = (int)tp;
+    // register-resident kernel for power-of-two pencils of at least 32 points
+    bool pow2 = pd.L >= 32 && pd.L <= kMaxPencil && (p->m < (i64(1) << 30));
+    for (int g = R.a; g < R.b; ++g) pow2 = pow2 && is_pow2(dg[g].n);
+    if (pow2) {
+      pd.kind = 1;
+      if (pd.S == 1) {
+        pd.P = 16;
+        pd.W = (int)std::max<i64>(1, 4096 / pd.L);
+        pd.split = 0;
+      } else {
+        int Wc = 64;
+        while (Wc > 1 && (pd.S % Wc != 0 || (i64)Wc * pd.L > 16384)) Wc /= 2;
+        pd.W = Wc;
+        pd.P = 16;
+        pd.split = ((i64)Wc * pd.L * 17 / 16 * 8 > 72 * 1024) ? 1 : 0;
+      }
+      if ((i64)pd.W * pd.L / pd.P > 1024) pd.kind = 0;
+    }
     pd.nst = 0;
     for (int g = R.a; g < R.b; ++g) {
       int stride = (int)range_count(dg, g + 1, R.b);
       i64 Ns = 1;
-      for (int r : radices_of(dg[g].n)) {
+      std::vector<int> rads = pd.kind == 1 ? pow2_radices(dg[g].n) : radices_of(dg[g].n);
+      for (int r : rads) {
         if (pd.nst >= kMaxStages) throw StatusError{E_UNSUPPORTED};
         StageDesc& s = pd.st[pd.nst++];
         s.radix = r;
@@ -251,6 +290,10 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
         s.stride = stride;
         s.Ns = (int)Ns;
         s.tw = tw.table(dg[g].n);
+        s.lg_r = ilog2(r);
+        s.lg_n = ilog2(dg[g].n);
+        s.lg_stride = ilog2(stride);
+        s.lg_Ns = ilog2(Ns);
         Ns *= r;
       }
     }
@@ -502,6 +545,7 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
       pd.out = out_grid ? E.out_grid : E.out_nat;
       pd.out.bstride = bout;
     }
+    TraceScope ts(pass_kernel_name(pd), 16.0 * (double)p->batch * (double)p->m, s);
     hipError_t e = launch_pass(pd, src, dst, s);
     if (e != hipSuccess) throw StatusError{E_HIP};
   }

@@ -12,6 +12,7 @@
 #include "wave.hpp"
 
 #include "kernels.hpp"
+#include "ktrace.hpp"
 
 namespace lfft {
 
@@ -37,6 +38,10 @@ Bufs carve(const WavePlan* w, void* ws) {
   b.FW = base + 2 * bm;
   return b;
 }
+
+// algorithmic bytes of one split/unsplit level: read 8 B and write 8 B per
+// complex point and batch element, plus 4 B of mask per point
+double split_bytes(long long B, long long ml) { return (16.0 * (double)B + 4.0) * (double)ml; }
 
 long long coeff_offset(const WavePlan* w, int level) {
   long long off = 0;
@@ -69,7 +74,10 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
     } else {
       next = (cur == b.F0) ? b.F1 : b.F0;
     }
-    check(launch_split(V.sd, B, cur, V.ml, masks[l], next, b.D2, half, s));
+    {
+      TraceScope ts("split_kernel", split_bytes(B, V.ml), s);
+      check(launch_split(V.sd, B, cur, V.ml, masks[l], next, b.D2, half, s));
+    }
     exec_lattice(V.fftN, true, false, false, b.D2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
     soff += B * V.ml;
     cur = next;
@@ -109,7 +117,10 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     } else {
       next = (cur == b.F0) ? b.F1 : b.F0;
     }
-    check(launch_unsplit(V.sd, B, cur, d2, half, masks[l], next, V.ml, s));
+    {
+      TraceScope ts("unsplit_kernel", split_bytes(B, V.ml), s);
+      check(launch_unsplit(V.sd, B, cur, d2, half, masks[l], next, V.ml, s));
+    }
     cur = next;
   }
   exec_lattice(w->fftM, true, false, false, cur, x, b.FW, w->lv[0].ml, m, s);

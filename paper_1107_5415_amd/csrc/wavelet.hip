@@ -12,6 +12,7 @@
 // exactly one writer.
 #include <hip/hip_runtime.h>
 
+#include "fft_common.hpp"
 #include "kernels.hpp"
 
 namespace lfft {
@@ -74,7 +75,7 @@ __device__ __forceinline__ Fiber fiber_of(const SplitDesc& sd, long long klin) {
 __global__ void split_kernel(SplitDesc sd, long long batch, const float2* __restrict__ ah,
                              long long ah_bs, const float* __restrict__ mask, float2* __restrict__ d1,
                              float2* __restrict__ d2, long long d_bs) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
   Fiber f = fiber_of(sd, k);
   const float a0 = mask[f.i0] * kInvSqrt2, a1 = mask[f.i1] * kInvSqrt2;
@@ -91,7 +92,7 @@ __global__ void unsplit_kernel(SplitDesc sd, long long batch, const float2* __re
                                const float2* __restrict__ d2, long long d_bs,
                                const float* __restrict__ mask, float2* __restrict__ ah,
                                long long ah_bs) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
   Fiber f = fiber_of(sd, k);
   const float a0 = mask[f.i0] * kInvSqrt2, a1 = mask[f.i1] * kInvSqrt2;
@@ -110,7 +111,7 @@ __global__ void split_mask_grad_kernel(SplitDesc sd, long long batch, const floa
                                        long long ah_bs, const float2* __restrict__ g1,
                                        const float2* __restrict__ g2, long long g_bs,
                                        float* __restrict__ gmask) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
   Fiber f = fiber_of(sd, k);
   const float2 c = cconj(f.phi);
@@ -132,7 +133,7 @@ __global__ void unsplit_mask_grad_kernel(SplitDesc sd, long long batch, const fl
                                          const float2* __restrict__ d2, long long d_bs,
                                          const float2* __restrict__ g, long long g_bs,
                                          float* __restrict__ gmask) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
   Fiber f = fiber_of(sd, k);
   float s0 = 0.f, s1 = 0.f;

@@ -30,7 +30,8 @@ EXPORTS = [
     "lfft_plan_info", "lfft_index_map", "lfft_workspace_size", "lfft_forward", "lfft_inverse",
     "lwt_plan_create", "lwt_plan_destroy", "lwt_level_info", "lwt_dirichlet_mask",
     "lwt_workspace_size", "lwt_saved_elems", "lwt_decompose", "lwt_reconstruct",
-    "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_strerror",
+    "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_trace_begin", "lfft_trace_end",
+    "lfft_trace_get", "lfft_strerror",
 ]
 
 _lib = None
@@ -77,6 +78,10 @@ def lib():
             "lwt_reconstruct": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
             "lwt_decompose_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
             "lwt_reconstruct_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+            "lfft_trace_begin": (ctypes.c_int, [ctypes.c_int]),
+            "lfft_trace_end": (ctypes.c_int, [_I32P]),
+            "lfft_trace_get": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                              ctypes.POINTER(ctypes.c_double), _FP]),
             "lfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
@@ -365,3 +370,23 @@ class WaveletPlan:
                                               _dptr(ws), _stream_handle(g.device)),
                "lwt_reconstruct_backward")
         return gc
+
+
+def trace_begin(capacity=100000):
+    """Start per-launch kernel timing (lfft_trace_begin)."""
+    _check(lib().lfft_trace_begin(int(capacity)), "lfft_trace_begin")
+
+
+def trace_end():
+    """Stop timing and return [(kernel, algorithmic_bytes, ms), ...]."""
+    n = ctypes.c_int()
+    _check(lib().lfft_trace_end(ctypes.byref(n)), "lfft_trace_end")
+    out = []
+    for i in range(n.value):
+        name = ctypes.c_char_p()
+        b = ctypes.c_double()
+        ms = ctypes.c_float()
+        _check(lib().lfft_trace_get(i, ctypes.byref(name), ctypes.byref(b), ctypes.byref(ms)),
+               "lfft_trace_get")
+        out.append((name.value.decode(), b.value, ms.value))
+    return out
