@@ -59,9 +59,28 @@ __device__ __forceinline__ float2 root16(int k, int sign) {
   return make_float2(C[k], sign < 0 ? -Sn[k] : Sn[k]);
 }
 
+// exp(sign * 2 pi i k / 32) for k in [0, 16): cos and sin of multiples of pi/16
+__device__ __forceinline__ float2 root32(int k, int sign) {
+  constexpr float C[16] = {1.0f, 0.98078528040323044913f, 0.92387953251128675613f,
+                           0.83146961230254523708f, 0.70710678118654752440f,
+                           0.55557023301960222474f, 0.38268343236508977173f,
+                           0.19509032201612826785f, 0.0f, -0.19509032201612826785f,
+                           -0.38268343236508977173f, -0.55557023301960222474f,
+                           -0.70710678118654752440f, -0.83146961230254523708f,
+                           -0.92387953251128675613f, -0.98078528040323044913f};
+  constexpr float Sn[16] = {0.0f, 0.19509032201612826785f, 0.38268343236508977173f,
+                            0.55557023301960222474f, 0.70710678118654752440f,
+                            0.83146961230254523708f, 0.92387953251128675613f,
+                            0.98078528040323044913f, 1.0f, 0.98078528040323044913f,
+                            0.92387953251128675613f, 0.83146961230254523708f,
+                            0.70710678118654752440f, 0.55557023301960222474f,
+                            0.38268343236508977173f, 0.19509032201612826785f};
+  return make_float2(C[k], sign < 0 ? -Sn[k] : Sn[k]);
+}
+
 template <int R>
 __device__ __forceinline__ void dft_pow2(float2* v, int sign) {
-  static_assert(R <= 16, "radix above 16");
+  static_assert(R <= 32, "radix above 32");
   // even/odd split: X[k] = E[k] + w^k O[k], X[k + R/2] = E[k] - w^k O[k]
   float2 e[R / 2], o[R / 2];
 #pragma unroll
@@ -73,7 +92,7 @@ __device__ __forceinline__ void dft_pow2(float2* v, int sign) {
   dft_pow2<R / 2>(o, sign);
 #pragma unroll
   for (int k = 0; k < R / 2; ++k) {
-    float2 t = c_mul(root16(k * (16 / R), sign), o[k]);
+    float2 t = (R == 32) ? c_mul(root32(k, sign), o[k]) : c_mul(root16(k * (16 / R), sign), o[k]);
     v[k] = c_add(e[k], t);
     v[k + R / 2] = c_sub(e[k], t);
   }

@@ -17,6 +17,7 @@
 
 #include "fft_common.hpp"
 #include "kernels.hpp"
+#include "ktrace.hpp"
 
 namespace lfft {
 namespace {
@@ -368,7 +369,9 @@ hipError_t launch_in(const PassDesc& p, const float2* in, float2* out, hipStream
 }  // namespace
 
 const char* fast_kernel_name(const PassDesc& p) {
-  return p.S > 1 ? "fft_fast_kernel<16, true" : "fft_fast_kernel<16, false";
+  const int min = p.in.mode == MAP_NATURAL ? 2 : 0;
+  return kernel_name_intern("fft_fast_kernel<16, %s, %s, %d, %d>", p.S > 1 ? "true" : "false",
+                            p.split ? "true" : "false", min, p.out.mode);
 }
 
 hipError_t launch_fast_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {

@@ -1,0 +1,466 @@
+// Persistent, register double-buffered FFT pass for single-digit power-of-two
+// pencils (the dominant case: the last axis of the eps-grid in rows, or one
+// outer axis in column tiles).
+//
+// Every workgroup stays resident and walks a contiguous range of tiles of
+// its XCD.  While tile t is transformed (radix-16/8/4/2 Stockham stages in
+// VGPRs, padded LDS transposes between stages), the global loads of tile
+// t + 1 are already in flight in a second register set, so the HBM stream
+// never waits for the arithmetic.  Pencil length L, pencils per tile W and
+// the radix sequence are compile-time constants, so all butterfly geometry
+// folds to constants and shifts.
+#include <hip/hip_runtime.h>
+
+#include "fft_common.hpp"
+#include "kernels.hpp"
+#include "ktrace.hpp"
+
+namespace lfft {
+namespace {
+using namespace dev;
+
+constexpr int kP = 32;  // values per thread
+constexpr bool kDoubleBufferRows = false;
+// workgroups per CU the register budget is sized for
+constexpr int kRowsWgPerCu = 2;
+constexpr int kColsWgPerCu = 1;
+// exchange real and imaginary parts separately for row tiles (halves LDS)
+constexpr bool kSplitRows = false;
+
+__device__ __forceinline__ int sphys(int e) { return e + (e >> 4); }
+
+// Radix sequence of a pencil of length L with 32 values per thread: a
+// radix-32 first stage (no twiddles) and radix-16/8 stages after it.
+__host__ __device__ constexpr int seq_radix(int L, int s) {
+  return L == 8192 ? (s == 0 ? 32 : 16)
+       : L == 4096 ? (s == 0 ? 32 : s == 1 ? 16 : 8)
+       : L == 2048 ? (s == 0 ? 32 : 8)
+       : L == 1024 ? 32
+       : L == 512 ? (s == 0 ? 32 : 16)
+       : 16;  // 256
+}
+__host__ __device__ constexpr int seq_len(int L) {
+  return (L == 8192 || L == 4096 || L == 2048) ? 3 : 2;
+}
+__host__ __device__ constexpr int seq_ns(int L, int s) {
+  return s == 0 ? 1 : seq_ns(L, s - 1) * seq_radix(L, s - 1);
+}
+template <int L, int S>
+struct StageR {
+  static constexpr int value = seq_radix(L, S);
+};
+template <int L>
+struct NStages {
+  static constexpr int value = seq_len(L);
+};
+template <int L, int S>
+struct StageNs {
+  static constexpr int value = seq_ns(L, S);
+};
+template <int R>
+struct Lg {
+  static constexpr int value = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
+};
+
+template <int MODE>
+struct Side {
+  long long lin;   // IDENTITY / LINEAR base, or batch offset for NATURAL
+  int c[4];        // NATURAL: To[o] (+) Ts[s]
+};
+
+template <int MODE>
+__device__ __forceinline__ void side_init(Side<MODE>& A, const MapDesc& m, long long b, int o, int s,
+                                          int L, int S) {
+  if constexpr (MODE == MAP_IDENTITY) {
+    A.lin = b * m.bstride + (long long)o * L * S + s;
+  } else if constexpr (MODE == MAP_LINEAR) {
+    A.lin = b * m.bstride + (long long)m.To[o].x + (long long)m.Ts[s].x;
+  } else {
+    A.c[0] = A.c[1] = A.c[2] = A.c[3] = 0;
+    gadd32(m, A.c, m.To[o]);
+    gadd32(m, A.c, m.Ts[s]);
+    A.lin = b * m.bstride;
+  }
+}
+
+// global index of positions l0 + i*step (i < R) on one side
+template <int MODE, int R, class F>
+__device__ __forceinline__ void side_positions(const Side<MODE>& A, const MapDesc& m, int S, int l0,
+                                               int step, F&& f) {
+  if constexpr (MODE == MAP_IDENTITY) {
+    const long long a = A.lin + (long long)l0 * S;
+#pragma unroll
+    for (int i = 0; i < R; ++i) f(i, a + (long long)(i * step) * S);
+  } else if constexpr (MODE == MAP_LINEAR) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) f(i, A.lin + (long long)m.Tl[l0 + i * step].x);
+  } else {
+    int c[4] = {A.c[0], A.c[1], A.c[2], A.c[3]};
+    gadd32(m, c, m.Tl[l0]);
+    const int4 D = m.Tl[step];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      f(i, A.lin + nat_index32(m, c));
+      if (i + 1 < R) gadd32(m, c, D);
+    }
+  }
+}
+
+struct TileId {
+  long long b;
+  int o, s;
+  bool active;
+};
+
+template <bool COLS>
+__device__ __forceinline__ TileId tile_pencil(long long tile, int w, int W, long long npen, int O,
+                                              int S) {
+  TileId t;
+  const long long pen = tile * W + w;
+  t.active = pen < npen;
+  const long long pp = t.active ? pen : 0;
+  const long long bo = pp / S;
+  t.s = (int)(pp - bo * S);
+  t.b = bo / O;
+  t.o = (int)(bo - t.b * O);
+  return t;
+}
+
+// loads of the first stage's inputs of one tile into v
+template <int L, int MIN>
+__device__ __forceinline__ void load_tile(float2* v, const PassDesc& p, const float2* __restrict__ in,
+                                          const TileId& t, int jt) {
+  constexpr int R = StageR<L, 0>::value;
+  constexpr int TPP = L / kP;
+  if (!t.active) {
+#pragma unroll
+    for (int i = 0; i < kP; ++i) v[i] = make_float2(0.f, 0.f);
+    return;
+  }
+  Side<MIN> A;
+  side_init<MIN>(A, p.in, t.b, t.o, t.s, L, p.S);
+#pragma unroll
+  for (int q = 0; q < kP / R; ++q) {
+    const int j = jt + TPP * q;
+    side_positions<MIN, R>(A, p.in, p.S, j, L / R,
+                           [&](int i, long long idx) { v[q * R + i] = in[idx]; });
+  }
+}
+
+template <int L, int SI>
+__device__ __forceinline__ void tw_load(float2* twb, const PassDesc& p, int jt) {
+  constexpr int R = StageR<L, SI>::value;
+  constexpr int Ns = StageNs<L, SI>::value;
+  constexpr int LG = Lg<R>::value;
+  constexpr int TPP = L / kP;
+  const float2* tw = p.st[0].tw;   // exp(-2 pi i k / L)
+#pragma unroll
+  for (int q = 0; q < kP / R; ++q) {
+    const int j = jt + TPP * q;
+    const int tstep = (j & (Ns - 1)) * (L / (Ns * R));
+#pragma unroll
+    for (int k = 0; k < LG; ++k) twb[q * LG + k] = tw[tstep << k];
+  }
+}
+
+// x[i] *= w^i for a block of N = 2^(K+1) inputs: bit K of i selects the
+// factor b[K] = w^(2^K); partial products are formed top-down so at most
+// K + 1 of them are live at any time.
+template <int N, int K>
+struct TwRec {
+  __device__ __forceinline__ static void run(float2* x, const float2* b, float2 part, bool has) {
+    TwRec<N / 2, K - 1>::run(x, b, part, has);
+    const float2 np = has ? c_mul(part, b[K]) : b[K];
+    TwRec<N / 2, K - 1>::run(x + N / 2, b, np, true);
+  }
+};
+template <int K>
+struct TwRec<1, K> {
+  __device__ __forceinline__ static void run(float2* x, const float2*, float2 part, bool has) {
+    if (has) x[0] = c_mul(x[0], part);
+  }
+};
+
+template <int R>
+__device__ __forceinline__ void apply_tw_s(float2* x, const float2* b, int sign) {
+  constexpr int LG = Lg<R>::value;
+  float2 bb[LG];
+#pragma unroll
+  for (int k = 0; k < LG; ++k) {
+    bb[k] = b[k];
+    if (sign > 0) bb[k].y = -bb[k].y;
+  }
+  TwRec<R, LG - 1>::run(x, bb, make_float2(1.f, 0.f), false);
+}
+
+template <int L, int SI>
+__device__ __forceinline__ void stage_compute(float2* v, const float2* twb, int sign) {
+  constexpr int R = StageR<L, SI>::value;
+  constexpr int LG = Lg<R>::value;
+#pragma unroll
+  for (int q = 0; q < kP / R; ++q) {
+    if constexpr (SI > 0) apply_tw_s<R>(&v[q * R], &twb[q * LG], sign);
+    dft_pow2<R>(&v[q * R], sign);
+  }
+}
+
+template <bool COLS, int L, int W>
+__device__ __forceinline__ int slds(int l, int w) {
+  return sphys(COLS ? l * W + w : w * L + l);
+}
+
+// write stage SI outputs, read stage SI+1 inputs (one part: 0 both, 1 re, 2 im)
+template <int L, int W, bool COLS, int SI, int PART>
+__device__ __forceinline__ void exch_write(const float2* v, void* lds, int jt, int w) {
+  constexpr int R = StageR<L, SI>::value;
+  constexpr int Ns = StageNs<L, SI>::value;
+  constexpr int TPP = L / kP;
+#pragma unroll
+  for (int q = 0; q < kP / R; ++q) {
+    const int j = jt + TPP * q;
+    const int out0 = (j / Ns) * Ns * R + (j & (Ns - 1));
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = slds<COLS, L, W>(out0 + i * Ns, w);
+      if constexpr (PART == 0)
+        static_cast<float2*>(lds)[e] = v[q * R + i];
+      else if constexpr (PART == 1)
+        static_cast<float*>(lds)[e] = v[q * R + i].x;
+      else
+        static_cast<float*>(lds)[e] = v[q * R + i].y;
+    }
+  }
+}
+
+template <int L, int W, bool COLS, int SI, int PART>
+__device__ __forceinline__ void exch_read(float2* v, const void* lds, int jt, int w) {
+  constexpr int R = StageR<L, SI>::value;
+  constexpr int TPP = L / kP;
+#pragma unroll
+  for (int q = 0; q < kP / R; ++q) {
+    const int j = jt + TPP * q;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = slds<COLS, L, W>(j + i * (L / R), w);
+      if constexpr (PART == 0)
+        v[q * R + i] = static_cast<const float2*>(lds)[e];
+      else if constexpr (PART == 1)
+        v[q * R + i].x = static_cast<const float*>(lds)[e];
+      else
+        v[q * R + i].y = static_cast<const float*>(lds)[e];
+    }
+  }
+}
+
+template <int L, int W, bool COLS, bool SPLIT, int SI>
+__device__ __forceinline__ void stages_from(float2* v, float2* twb, void* lds, const PassDesc& p,
+                                            int jt, int w) {
+  constexpr int NS = NStages<L>::value;
+  stage_compute<L, SI>(v, twb, p.sign);
+  if constexpr (SI + 1 < NS) {
+    tw_load<L, SI + 1>(twb, p, jt);
+    if constexpr (!SPLIT) {
+      exch_write<L, W, COLS, SI, 0>(v, lds, jt, w);
+      __syncthreads();
+      exch_read<L, W, COLS, SI + 1, 0>(v, lds, jt, w);
+      __syncthreads();
+    } else {
+      exch_write<L, W, COLS, SI, 1>(v, lds, jt, w);
+      __syncthreads();
+      exch_read<L, W, COLS, SI + 1, 1>(v, lds, jt, w);
+      __syncthreads();
+      exch_write<L, W, COLS, SI, 2>(v, lds, jt, w);
+      __syncthreads();
+      exch_read<L, W, COLS, SI + 1, 2>(v, lds, jt, w);
+      __syncthreads();
+    }
+    stages_from<L, W, COLS, SPLIT, SI + 1>(v, twb, lds, p, jt, w);
+  }
+}
+
+template <int L, int MOUT>
+__device__ __forceinline__ void store_tile(const float2* v, const PassDesc& p,
+                                           float2* __restrict__ out, const TileId& t, int jt) {
+  constexpr int NS = NStages<L>::value;
+  constexpr int R = StageR<L, NS - 1>::value;
+  constexpr int Ns = StageNs<L, NS - 1>::value;
+  constexpr int TPP = L / kP;
+  if (!t.active) return;
+  Side<MOUT> A;
+  side_init<MOUT>(A, p.out, t.b, t.o, t.s, L, p.S);
+#pragma unroll
+  for (int q = 0; q < kP / R; ++q) {
+    const int j = jt + TPP * q;
+    const int out0 = (j / Ns) * Ns * R + (j & (Ns - 1));
+    side_positions<MOUT, R>(A, p.out, p.S, out0, Ns, [&](int i, long long idx) {
+      float2 x = v[q * R + i];
+      if (p.post) {
+        const int l = out0 + i * Ns;
+        const long long lo = (t.s / p.lo_div) % p.lo_n;
+        const long long tt = ((long long)l * lo) % p.postN;
+        float2 wv = c_mul(p.tw_hi[tt >> 12], p.tw_lo[tt & 4095]);
+        if (p.sign > 0) wv.y = -wv.y;
+        x = c_mul(x, wv);
+      }
+      x.x *= p.scale;
+      x.y *= p.scale;
+      out[idx] = x;
+    });
+  }
+}
+
+template <int L, int W, bool COLS, bool SPLIT, int MIN, int MOUT>
+__global__ void __launch_bounds__(W * L / kP, (COLS ? kColsWgPerCu : kRowsWgPerCu)) fft_stream_kernel(PassDesc p, const float2* __restrict__ in,
+                                                                float2* __restrict__ out) {
+  extern __shared__ float2 lds_raw[];
+  void* lds = lds_raw;
+  constexpr int TPP = L / kP;
+  const int tid = threadIdx.x;
+  const int w = COLS ? tid % W : tid / TPP;
+  const int jt = COLS ? tid / W : tid % TPP;
+  const long long npen = p.batch * (long long)p.O * p.S;
+  const long long ntiles = (npen + W - 1) / W;
+  // persistent schedule: XCD x owns tiles [beg_x, end_x); its k-th workgroup
+  // takes beg_x + k, beg_x + k + nwg_x, ...
+  const long long G = gridDim.x;
+  const long long x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const long long nwg_x = (G >> 3) + ((G & 7) > x ? 1 : 0);
+  const long long per = ntiles >> 3, rem = ntiles & 7;
+  const long long beg = x * per + (x < rem ? x : rem);
+  const long long end = beg + per + (x < rem ? 1 : 0);
+  long long tile = beg + k;
+  if (tile >= end) return;
+
+  float2 twb[16];
+  if constexpr (kDoubleBufferRows && !COLS) {
+    // rows: register double buffering, the loads of the next tile are in
+    // flight while this tile is transformed
+    float2 va[kP], vb[kP];
+    TileId ta = tile_pencil<COLS>(tile, w, W, npen, p.O, p.S);
+    load_tile<L, MIN>(va, p, in, ta, jt);
+    for (;;) {
+      const long long nxt = tile + nwg_x;
+      const bool more = nxt < end;
+      TileId tb;
+      if (more) {
+        tb = tile_pencil<COLS>(nxt, w, W, npen, p.O, p.S);
+        load_tile<L, MIN>(vb, p, in, tb, jt);
+      }
+      stages_from<L, W, COLS, SPLIT, 0>(va, twb, lds, p, jt, w);
+      store_tile<L, MOUT>(va, p, out, ta, jt);
+      if (!more) break;
+#pragma unroll
+      for (int i = 0; i < kP; ++i) va[i] = vb[i];
+      ta = tb;
+      tile = nxt;
+    }
+  } else {
+    // column tiles: one register set
+    float2 va[kP];
+    for (; tile < end; tile += nwg_x) {
+      TileId ta = tile_pencil<COLS>(tile, w, W, npen, p.O, p.S);
+      load_tile<L, MIN>(va, p, in, ta, jt);
+      stages_from<L, W, COLS, SPLIT, 0>(va, twb, lds, p, jt, w);
+      store_tile<L, MOUT>(va, p, out, ta, jt);
+    }
+  }
+}
+
+int g_cus = 0;
+
+template <int L, int W, bool COLS, bool SPLIT, int MIN, int MOUT>
+hipError_t launch_t(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
+  auto kern = fft_stream_kernel<L, W, COLS, SPLIT, MIN, MOUT>;
+  constexpr int NT = W * L / kP;
+  constexpr int tile = W * L;
+  constexpr size_t lds = (size_t)(tile + tile / 16 + 1) * (SPLIT ? sizeof(float) : sizeof(float2));
+  static int wgs_per_cu = 0;
+  if (!wgs_per_cu) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds);
+    if (e != hipSuccess) return e;
+    wgs_per_cu = nb > 0 ? nb : 1;
+  }
+  if (!g_cus) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  const long long npen = p.batch * (long long)p.O * p.S;
+  const long long ntiles = (npen + W - 1) / W;
+  long long grid = (long long)g_cus * wgs_per_cu;
+  if (grid > ntiles) grid = ntiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, p, in, out);
+  return hipGetLastError();
+}
+
+template <int L, int W, bool COLS, bool SPLIT, int MIN>
+hipError_t launch_o(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
+  switch (p.out.mode) {
+    case MAP_IDENTITY: return launch_t<L, W, COLS, SPLIT, MIN, MAP_IDENTITY>(p, in, out, s);
+    case MAP_LINEAR: return launch_t<L, W, COLS, SPLIT, MIN, MAP_LINEAR>(p, in, out, s);
+    default: return launch_t<L, W, COLS, SPLIT, MIN, MAP_NATURAL>(p, in, out, s);
+  }
+}
+
+template <int L, int W, bool COLS>
+hipError_t launch_i(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
+  constexpr bool SPLIT = (COLS || kSplitRows) ? ((long long)W * L * 17 / 16 * 8 > 72 * 1024 || kSplitRows)
+                                              : false;
+  if (p.in.mode == MAP_NATURAL) return launch_o<L, W, COLS, SPLIT, MAP_NATURAL>(p, in, out, s);
+  return launch_o<L, W, COLS, SPLIT, MAP_IDENTITY>(p, in, out, s);
+}
+
+}  // namespace
+
+// (L, W) shapes with a compiled streaming kernel; see plan.cpp
+bool stream_supported(int L, int W, bool cols) {
+  if (!cols) {
+    return (L == 8192 && W == 1) || (L == 4096 && W == 1) || (L == 2048 && W == 2) ||
+           (L == 1024 && W == 4) || (L == 512 && W == 8) || (L == 256 && W == 16);
+  }
+  return (L == 2048 && W == 8) || (L == 1024 && W == 16) || (L == 512 && W == 32) ||
+         (L == 256 && W == 64) || (L == 4096 && W == 4);
+}
+
+const char* stream_kernel_name(const PassDesc& p) {
+  // the template arguments exactly as the profiler prints the symbol
+  const bool cols = p.S > 1;
+  const int W = cols ? (p.L == 4096 ? 4 : 16384 / p.L) : (p.L >= 4096 ? 1 : 4096 / p.L);
+  const bool split = (cols || kSplitRows) ? ((long long)W * p.L * 17 / 16 * 8 > 72 * 1024 || kSplitRows)
+                                          : false;
+  const int min = p.in.mode == MAP_NATURAL ? 2 : 0;
+  const int mout = p.out.mode;
+  return kernel_name_intern("fft_stream_kernel<%d, %d, %s, %s, %d, %d>", p.L, W,
+                            cols ? "true" : "false", split ? "true" : "false", min, mout);
+}
+
+hipError_t launch_stream_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
+  const bool cols = p.S > 1;
+  if (!cols) {
+    switch (p.L) {
+      case 8192: return launch_i<8192, 1, false>(p, in, out, s);
+      case 4096: return launch_i<4096, 1, false>(p, in, out, s);
+      case 2048: return launch_i<2048, 2, false>(p, in, out, s);
+      case 1024: return launch_i<1024, 4, false>(p, in, out, s);
+      case 512: return launch_i<512, 8, false>(p, in, out, s);
+      case 256: return launch_i<256, 16, false>(p, in, out, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p.L) {
+    case 4096: return launch_i<4096, 4, true>(p, in, out, s);
+    case 2048: return launch_i<2048, 8, true>(p, in, out, s);
+    case 1024: return launch_i<1024, 16, true>(p, in, out, s);
+    case 512: return launch_i<512, 32, true>(p, in, out, s);
+    case 256: return launch_i<256, 64, true>(p, in, out, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lfft

@@ -15,6 +15,11 @@ const char* pass_kernel_name(const PassDesc& p);
 // Register-resident power-of-two pass (descriptor kind 1).
 hipError_t launch_fast_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s);
 const char* fast_kernel_name(const PassDesc& p);
+// Persistent double-buffered pass for single-digit power-of-two pencils
+// (descriptor kind 2) and the (L, W) shapes it is compiled for.
+hipError_t launch_stream_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s);
+bool stream_supported(int L, int W, bool cols);
+const char* stream_kernel_name(const PassDesc& p);
 
 // Fourier-domain wavelet split of one level (Section 5.3, step 4).
 hipError_t launch_split(const SplitDesc& sd, long long batch, const float2* ahat, long long ah_bs,

@@ -1,7 +1,11 @@
 // Per-launch kernel timing; see ktrace.hpp and the lfft_trace_* entry points.
 #include "ktrace.hpp"
 
+#include <cstdarg>
+#include <cstdio>
 #include <mutex>
+#include <set>
+#include <string>
 #include <vector>
 
 #include "lfft.h"
@@ -26,6 +30,18 @@ State& st() {
 }  // namespace
 
 bool trace_on() { return st().on; }
+
+const char* kernel_name_intern(const char* fmt, ...) {
+  static std::mutex mu;
+  static std::set<std::string> names;
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::lock_guard<std::mutex> g(mu);
+  return names.insert(buf).first->c_str();
+}
 
 int trace_begin(const char* kernel, double bytes, hipStream_t s) {
   State& S = st();

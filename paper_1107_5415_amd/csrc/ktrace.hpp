@@ -8,6 +8,8 @@
 namespace lfft {
 
 bool trace_on();
+// Stable storage for a formatted kernel name (deduplicated, never freed).
+const char* kernel_name_intern(const char* fmt, ...);
 // Returns a slot index for a launch about to be enqueued on `s`, or -1.
 int trace_begin(const char* kernel, double bytes, hipStream_t s);
 void trace_end(int slot, hipStream_t s);

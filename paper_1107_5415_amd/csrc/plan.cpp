@@ -276,6 +276,7 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
         pd.split = ((i64)Wc * pd.L * 17 / 16 * 8 > 72 * 1024) ? 1 : 0;
       }
       if ((i64)pd.W * pd.L / pd.P > 1024) pd.kind = 0;
+      if (pd.kind == 1 && R.b - R.a == 1 && stream_supported(pd.L, pd.W, pd.S > 1)) pd.kind = 2;
     }
     pd.nst = 0;
     for (int g = R.a; g < R.b; ++g) {
@@ -545,7 +546,8 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
       pd.out = out_grid ? E.out_grid : E.out_nat;
       pd.out.bstride = bout;
     }
-    TraceScope ts(pass_kernel_name(pd), 16.0 * (double)p->batch * (double)p->m, s);
+    TraceScope ts(trace_on() ? pass_kernel_name(pd) : nullptr,
+                  16.0 * (double)p->batch * (double)p->m, s);
     hipError_t e = launch_pass(pd, src, dst, s);
     if (e != hipSuccess) throw StatusError{E_HIP};
   }
