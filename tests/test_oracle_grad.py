@@ -1,0 +1,74 @@
+"""Pins of the FP64 torch gradient oracle: forward values equal the numpy
+oracle, Parseval's closed-form gradient, and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dft, grad as G, lattice as L, wavelet as W
+import workloads
+
+
+@pytest.mark.parametrize("M", [((32, 8), (-8, 32)), ((5, 2), (1, 3)), ((3, 1, 0), (0, 3, 1), (1, 0, 3)),
+                               ((16, 8), (0, 16))])
+def test_torch_fft_matches_oracle(M):
+    m = abs(L.det(M))
+    x = workloads.complex_normal(1, (2, m), np.complex128)
+    p = G.TorchPair(M)
+    X = p.forward(torch.from_numpy(x)).numpy()
+    np.testing.assert_allclose(X, dft.lattice_dft_direct(M, x), atol=1e-12)
+    np.testing.assert_allclose(p.inverse(torch.from_numpy(X)).numpy(), x, atol=1e-12)
+
+
+def test_parseval_gradient_closed_form():
+    """grad_x ||F(M) x||^2 = 2 x (F unitary)."""
+    M = ((12, 4), (0, 6))
+    x = torch.from_numpy(workloads.complex_normal(2, (1, 72), np.complex128)).requires_grad_(True)
+    y = G.TorchPair(M).forward(x)
+    torch.sum(y.real ** 2 + y.imag ** 2).backward()
+    np.testing.assert_allclose(x.grad.numpy(), 2 * x.detach().numpy(), atol=1e-12)
+
+
+CASES = [(((16, 8), (0, 16)), workloads.J_QUINCUNX, 3), (((12, 4), (0, 6)), workloads.J_X, 1),
+         (((32, 8), (-8, 32)), workloads.J_QUINCUNX, 1)]
+
+
+@pytest.mark.parametrize("M,J,levels", CASES)
+def test_pyramid_forward_matches_oracle(M, J, levels):
+    m = abs(L.det(M))
+    x = workloads.complex_normal(3, (2, m), np.complex128)
+    masks = W.default_masks(M, J, levels)
+    pyr = G.TorchPyramid(M, J, levels)
+    mt = [torch.from_numpy(mk) for mk in masks]
+    c = pyr.decompose(torch.from_numpy(x), mt).numpy()
+    np.testing.assert_allclose(c, W.decompose(x, M, J, levels), atol=1e-12)
+    np.testing.assert_allclose(pyr.reconstruct(torch.from_numpy(c), mt).numpy(),
+                               W.reconstruct(c, M, J, levels), atol=1e-12)
+
+
+@pytest.mark.parametrize("M,J,levels", CASES)
+def test_gradients_finite_differences(M, J, levels):
+    """Central differences in FP64 along random directions of the samples and
+    of the (non-QMF, perturbed) masks."""
+    m = abs(L.det(M))
+    rng = np.random.default_rng(4)
+    x = workloads.complex_normal(5, (2, m), np.complex128)
+    target = workloads.complex_normal(6, (2, m), np.complex128)
+    masks = [mk + 0.1 * rng.standard_normal(mk.shape) for mk in W.default_masks(M, J, levels)]
+    weights = [1.0 + 0.5 * l for l in range(levels)]
+    loss, gx, gm = G.loss_and_grads(M, J, levels, x, masks, target, weights)
+    pyr = G.TorchPyramid(M, J, levels)
+
+    def Lf(xx, mm):
+        with torch.no_grad():
+            return float(G.pyramid_loss(pyr, torch.from_numpy(xx), [torch.from_numpy(a) for a in mm],
+                                        torch.from_numpy(target), weights))
+    v = workloads.complex_normal(7, (2, m), np.complex128)
+    h = 1e-3   # the loss is quadratic in x: central differences are exact up to rounding
+    fd = (Lf(x + h * v, masks) - Lf(x - h * v, masks)) / (2 * h)
+    an = float(np.sum((np.conj(gx) * v).real))
+    assert abs(fd - an) <= 1e-9 * max(1.0, abs(an))
+    u = [rng.standard_normal(mk.shape) for mk in masks]
+    h = 1e-5
+    fd = (Lf(x, [a + h * b for a, b in zip(masks, u)]) - Lf(x, [a - h * b for a, b in zip(masks, u)])) / (2 * h)
+    an = float(sum(np.sum(g * b) for g, b in zip(gm, u)))
+    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
