@@ -182,6 +182,78 @@ int lwt_reconstruct_backward(lwt_plan_t plan, const void* grad_samples, const vo
                              const float* const* masks, void* grad_coeffs,
                              float* const* grad_masks, void* workspace, hipStream_t stream);
 
+/* ---- batched transforms on patterns of different M ---------------------- */
+
+/* Many lattices in one call: the signals of lattices M_0 .. M_{count-1}
+ * (each d x d, row-major, stored one after another in Ms) are concatenated,
+ * signal i holding m_i = |det M_i| complex64 values at element offset
+ * offsets[i] = m_0 + ... + m_{i-1}.  Every lattice is transformed
+ * independently (Section 4.2: the blocks of the Kronecker form are
+ * independent), natural order in and out, with the unitary transform of
+ * lfft_forward / lfft_inverse.  The plan holds, for the configuration in
+ * use, a fixed-tile schedule of every lattice whose elementary divisors are
+ * powers of two and 32 <= m_i <= 2^(2 tile_lg); other lattices run through
+ * their own lfft plan after the batched launch. */
+typedef struct lfft_batch_s* lfft_batch_t;
+
+#define LFFT_BATCH_LOOP 0        /* one lfft launch sequence per lattice      */
+#define LFFT_BATCH_PERSISTENT 1  /* one persistent kernel over all lattices   */
+#define LFFT_BATCH_GRAPH 2       /* the persistent launch as a HIP graph,
+                                    captured on first use for each (direction,
+                                    in, out, workspace) and replayed after    */
+
+/* Create a batch plan (default configuration tile_lg 12, order 0).  flags:
+ * 0 or LFFT_HOST_ONLY (schedules only; execute/tune/status return
+ * LFFT_E_STATE).  Errors: ARG, SINGULAR, OVERFLOW, UNSUPPORTED (some
+ * m_i >= 2^31 or sum m_i >= 2^40), NOMEM, HIP. */
+int lfft_batch_create(lfft_batch_t* plan, int count, int d, const int64_t* Ms, uint32_t flags);
+int lfft_batch_destroy(lfft_batch_t plan);
+
+/* offsets[count + 1]: element offset of every signal and the total (host). */
+int lfft_batch_offsets(lfft_batch_t plan, int64_t* offsets);
+
+/* Workspace bytes of lfft_batch_execute / lfft_batch_tune (8 * sum m_i). */
+size_t lfft_batch_workspace_size(lfft_batch_t plan);
+
+/* Select a configuration: tiles of 2^tile_lg elements (11, 12 or 13) and
+ * order bits (bit 0: strided pass first when there is no four-step split;
+ * bit 1: smallest radix first inside a digit; bit 2: split the pass
+ * boundary inside an axis even where an axis boundary fits).  Rebuilds the
+ * schedules and the device queues; drops captured graphs.  Errors: ARG. */
+int lfft_batch_configure(lfft_batch_t plan, int tile_lg, int order);
+
+/* Configuration in use and the number of lattices it schedules in the
+ * batched launch (host outputs, any may be NULL). */
+int lfft_batch_config(lfft_batch_t plan, int* tile_lg, int* order, int* eligible);
+
+/* Fixed-tile schedule of lattice i (forward): number of passes (0 if the
+ * lattice is not in the batched launch), and per pass (at most 2) the
+ * pencil length, the number of tiles and whether the four-step twiddle
+ * follows it (host outputs). */
+int lfft_batch_schedule(lfft_batch_t plan, int i, int* passes, int64_t* pencil, int64_t* tiles,
+                        int* post);
+
+/* Autotuner: time every candidate configuration (tile_lg in {11, 12, 13},
+ * order in {0, 1, 2, 3}) with the persistent launch on the caller's buffers
+ * (reps timed runs each, minimum kept), keep the fastest, and remember it
+ * for this process keyed by the list of matrices: a later call with the
+ * same matrices applies the remembered choice without timing
+ * (*best_ms = -1).  Overwrites out and the workspace.  Synchronises. */
+int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspace, int reps,
+                    float* best_ms, hipStream_t stream);
+
+/* out = F(M_i) in (inverse != 0: F(M_i)^{-1}) for every lattice, in device
+ * complex64 [sum m_i], out of place, on `stream`.  mode: LFFT_BATCH_*.
+ * Calls on one plan must not overlap in time (they share the queue heads
+ * and counters).  Errors: ARG, STATE (host-only plan), HIP. */
+int lfft_batch_execute(lfft_batch_t plan, int inverse, int mode, const void* in, void* out,
+                       void* workspace, hipStream_t stream);
+
+/* Error flag of the persistent launch: non-zero if a dependency wait ever
+ * exceeded its spin limit (the results of that call are then invalid).
+ * Synchronises the device and clears the flag. */
+int lfft_batch_status(lfft_batch_t plan, int* error_flag);
+
 /* ---- per-launch kernel timing (tracing) -------------------------------- */
 
 /* Start recording every kernel this library launches from now on (process

@@ -34,8 +34,21 @@ def sources():
     return out
 
 
-def _compile(src):
+def _headers_mtime():
+    t = 0.0
+    for d in (CSRC, INCLUDE):
+        for f in os.listdir(d):
+            if f.endswith(".hpp") or f.endswith(".h"):
+                t = max(t, os.path.getmtime(os.path.join(d, f)))
+    return t
+
+
+def _compile(src, force=True):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not force and os.path.exists(obj):
+        newest = max(os.path.getmtime(src), _headers_mtime())
+        if os.path.getmtime(obj) >= newest:
+            return obj
     cmd = [HIPCC] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE
@@ -48,11 +61,13 @@ def _compile(src):
     return obj
 
 
-def build_library(verbose=False, jobs=8):
+def build_library(verbose=False, jobs=8, force=True):
+    """Compile every source (force=False: only objects older than their
+    source or any header) and link liblfft.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lamdhip64"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -65,5 +80,5 @@ def build_library(verbose=False, jobs=8):
 
 
 if __name__ == "__main__":
-    build_library(verbose=True)
+    build_library(verbose=True, force="--incremental" not in sys.argv)
     sys.exit(0)

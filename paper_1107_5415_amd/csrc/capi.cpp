@@ -4,6 +4,7 @@
 
 #include <new>
 
+#include "batch.hpp"
 #include "plan.hpp"
 #include "wave.hpp"
 
@@ -12,6 +13,9 @@ struct lfft_plan_s {
 };
 struct lwt_plan_s {
   lfft::WavePlan* w;
+};
+struct lfft_batch_s {
+  lfft::BatchPlan* b;
 };
 
 namespace {
@@ -253,6 +257,89 @@ int lwt_reconstruct_backward(lwt_plan_t plan, const void* grad_samples, const vo
                                     static_cast<float2*>(grad_coeffs), grad_masks, workspace,
                                     stream);
   });
+}
+
+int lfft_batch_create(lfft_batch_t* plan, int count, int d, const int64_t* Ms, uint32_t flags) {
+  if (!plan) return LFFT_E_ARG;
+  *plan = nullptr;
+  if (flags & ~LFFT_HOST_ONLY) return LFFT_E_ARG;
+  if (d > lfft::kMaxD) return LFFT_E_UNSUPPORTED;
+  lfft::BatchPlan* b = nullptr;
+  int st = guarded([&] { b = lfft::build_batch_plan(count, d, Ms, flags); });
+  if (st != LFFT_OK) return st;
+  *plan = new (std::nothrow) lfft_batch_s{b};
+  if (!*plan) {
+    lfft::free_batch_plan(b);
+    return LFFT_E_NOMEM;
+  }
+  return LFFT_OK;
+}
+
+int lfft_batch_destroy(lfft_batch_t plan) {
+  if (!plan) return LFFT_OK;
+  lfft::free_batch_plan(plan->b);
+  delete plan;
+  return LFFT_OK;
+}
+
+int lfft_batch_offsets(lfft_batch_t plan, int64_t* offsets) {
+  if (!plan || !offsets) return LFFT_E_ARG;
+  for (size_t i = 0; i < plan->b->off.size(); ++i) offsets[i] = plan->b->off[i];
+  return LFFT_OK;
+}
+
+size_t lfft_batch_workspace_size(lfft_batch_t plan) {
+  if (!plan) return 0;
+  return plan->b->ws_elems * 8;
+}
+
+int lfft_batch_configure(lfft_batch_t plan, int tile_lg, int order) {
+  if (!plan) return LFFT_E_ARG;
+  return guarded([&] { lfft::configure_batch(plan->b, tile_lg, order); });
+}
+
+int lfft_batch_config(lfft_batch_t plan, int* tile_lg, int* order, int* eligible) {
+  if (!plan) return LFFT_E_ARG;
+  if (tile_lg) *tile_lg = plan->b->tile_lg;
+  if (order) *order = plan->b->order;
+  if (eligible) *eligible = plan->b->eligible;
+  return LFFT_OK;
+}
+
+int lfft_batch_schedule(lfft_batch_t plan, int i, int* passes, int64_t* pencil, int64_t* tiles,
+                        int* post) {
+  if (!plan || i < 0 || i >= plan->b->count || !passes) return LFFT_E_ARG;
+  const lfft::LatticePlan* p = plan->b->tiled[i];
+  *passes = p ? (int)p->fwd.passes.size() : 0;
+  if (!p) return LFFT_OK;
+  for (int k = 0; k < *passes && k < 2; ++k) {
+    const lfft::PassDesc& pd = p->fwd.passes[k];
+    if (pencil) pencil[k] = pd.L;
+    if (tiles) tiles[k] = ((int64_t)pd.O * pd.S + pd.W - 1) / pd.W;
+    if (post) post[k] = pd.post;
+  }
+  return LFFT_OK;
+}
+
+int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspace, int reps,
+                    float* best_ms, hipStream_t stream) {
+  if (!plan || !in || !out || in == out || !workspace || reps < 1) return LFFT_E_ARG;
+  if (!plan->b->dctl) return LFFT_E_STATE;
+  return guarded([&] { lfft::tune_batch(plan->b, in, out, workspace, reps, stream, best_ms); });
+}
+
+int lfft_batch_execute(lfft_batch_t plan, int inverse, int mode, const void* in, void* out,
+                       void* workspace, hipStream_t stream) {
+  if (!plan || !in || !out || in == out || !workspace) return LFFT_E_ARG;
+  if (mode < LFFT_BATCH_LOOP || mode > LFFT_BATCH_GRAPH) return LFFT_E_ARG;
+  if (!plan->b->dctl) return LFFT_E_STATE;
+  return guarded([&] { lfft::exec_batch(plan->b, inverse != 0, mode, in, out, workspace, stream); });
+}
+
+int lfft_batch_status(lfft_batch_t plan, int* error_flag) {
+  if (!plan || !error_flag) return LFFT_E_ARG;
+  if (!plan->b->dctl) return LFFT_E_STATE;
+  return guarded([&] { *error_flag = lfft::batch_error_flag(plan->b, true); });
 }
 
 const char* lfft_strerror(int status) {

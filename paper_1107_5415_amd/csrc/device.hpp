@@ -53,16 +53,39 @@ struct PassDesc {
   StageDesc st[kMaxStages];
   int sign;                   // -1 forward, +1 inverse
   float scale;                // applied when storing
-  // four-step twiddle after the stages: x = (l * lo) mod postN with
-  // lo = (s / lo_div) % lo_n, factor exp(sign 2 pi i x / postN) from the
-  // two-level table tw_hi[x >> 12] * tw_lo[x & 4095]
+  // four-step twiddle after the stages: x = ((l mod post_lmod) * lo) mod
+  // postN with lo = (s / lo_div) % lo_n, factor exp(sign 2 pi i x / postN)
+  // from the two-level table tw_hi[x >> 12] * tw_lo[x & 4095]; the high digit
+  // is the last (fastest) digit of the pencil, of length post_lmod
   int post;
   int postN;
+  int post_lmod;
   int lo_div;
   int lo_n;
   const float2* tw_hi;
   const float2* tw_lo;
   MapDesc in, out;
+};
+
+// One pass of one lattice in the batched persistent launch.  Buffers are
+// selected by index (0 caller input, 1 caller output, 2 workspace) so the
+// descriptors do not depend on the call's pointers.
+struct BatchPass {
+  PassDesc pd;                // batch 1, maps and batch strides resolved
+  long long in_off, out_off;  // element offsets of the lattice's signal
+  int in_buf, out_buf;
+  int inst;                   // dependency counter of the lattice
+  int need;                   // finished tiles of its first pass required first (0: none)
+  int signal;                 // 1: count every finished tile in the counter
+  int variant;                // body: BATCH_ROWS_NN .. BATCH_COLS_IN
+};
+
+enum BatchVariant : int {
+  BATCH_ROWS_NN = 0,          // contiguous pencils, natural in, natural out (one-pass lattice)
+  BATCH_ROWS_NI = 1,          // contiguous pencils, natural in, grid out
+  BATCH_COLS_NI = 2,          // strided pencils, natural in, grid out
+  BATCH_ROWS_IN = 3,          // contiguous pencils, grid in, natural out
+  BATCH_COLS_IN = 4,          // strided pencils, grid in, natural out
 };
 
 // One level of the Fourier-domain wavelet split (natural orders).

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) pass_generic_kernel(PassDesc p, const flo
     float2 v = A[e];
     if (p.post) {
       long long lo = (s / p.lo_div) % p.lo_n;
-      long long x = ((long long)l * lo) % p.postN;
+      long long x = ((long long)(l % p.post_lmod) * lo) % p.postN;
       float2 w = c_mul(p.tw_hi[x >> 12], p.tw_lo[x & 4095]);
       if (p.sign > 0) w = c_conj(w);
       v = c_mul(v, w);

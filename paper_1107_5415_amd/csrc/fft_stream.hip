@@ -295,7 +295,7 @@ __device__ __forceinline__ void store_tile(const float2* v, const PassDesc& p,
     side_positions<MOUT, R>(A, p.out, p.S, out0, Ns, [&](int i, long long idx) {
       float2 x = v[q * R + i];
       if (p.post) {
-        const int l = out0 + i * Ns;
+        const int l = (out0 + i * Ns) % p.post_lmod;
         const long long lo = (t.s / p.lo_div) % p.lo_n;
         const long long tt = ((long long)l * lo) % p.postN;
         float2 wv = c_mul(p.tw_hi[tt >> 12], p.tw_lo[tt & 4095]);

@@ -21,6 +21,17 @@ hipError_t launch_stream_pass(const PassDesc& p, const float2* in, float2* out, 
 bool stream_supported(int L, int W, bool cols);
 const char* stream_kernel_name(const PassDesc& p);
 
+// Batched persistent launch over the BatchPass/item queues (tile_lg 11..13:
+// tiles of 2^tile_lg elements, 2^tile_lg / 16 threads per workgroup).
+// ctl: 8 queue heads, then the error flag at ctl[8]; counters: one per lattice.
+hipError_t launch_batch(int tile_lg, const BatchPass* passes, const int2* items, const int* qbeg,
+                        int* ctl, int* counters, const float2* in, float2* out, float2* ws,
+                        int spin_limit, int grid, hipStream_t s);
+hipError_t launch_batch_clear(int* ctl, int* counters, int n, hipStream_t s);
+size_t batch_lds_bytes(int tile);
+int batch_occupancy(int tile_lg);        // resident workgroups per CU (0 on error)
+const char* batch_kernel_name(int tile_lg);
+
 // Fourier-domain wavelet split of one level (Section 5.3, step 4).
 hipError_t launch_split(const SplitDesc& sd, long long batch, const float2* ahat, long long ah_bs,
                         const float* mask, float2* d1, float2* d2, long long d_bs, hipStream_t s);

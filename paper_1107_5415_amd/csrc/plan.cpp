@@ -8,6 +8,7 @@
 // coordinate vectors and look up FP32 twiddles built in FP64.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -238,6 +239,78 @@ MapDesc identity_map() {
   return m;
 }
 
+// Schedule for fixed tiles of T = 2^tile_lg elements (the batched persistent
+// launch): every pass is one power-of-two pencil of 32..T points, so every
+// pass runs the register-resident kernel with W = T / L pencils per tile.
+// A lattice of m <= T points is one pass.  Otherwise the digits split into a
+// leading and a trailing chunk of at most T points each; the boundary lies on
+// an axis boundary when one is in range (order bit 2 clear), else in the
+// middle of an axis, which is then done four-step: its high digit closes the
+// leading chunk and its low digit opens the trailing one.
+void tiled_schedule(LatticePlan* p) {
+  const int T = p->tile_lg;
+  std::vector<int> lg;
+  int s = 0;
+  for (i64 e : p->eps) {
+    if (!is_pow2(e)) throw StatusError{E_UNSUPPORTED};
+    lg.push_back(ilog2(e));
+    s += lg.back();
+  }
+  if (s < 5 || s > 2 * T) throw StatusError{E_UNSUPPORTED};
+  const int n = (int)lg.size();
+  if (s <= T) {
+    for (int j = 0; j < n; ++j) p->digits.push_back(Digit{j, p->eps[j], 0, 1, 1});
+    p->ranges.push_back(PassRange{0, (int)p->digits.size(), false, 0});
+    return;
+  }
+  // c = log2 of the trailing chunk
+  const int lo_c = std::max(5, s - T), hi_c = std::min(T, s - 5);
+  int c = -1;
+  if (!(p->order & 4)) {
+    int suf = 0;
+    for (int k = n - 1; k >= 1; --k) {
+      suf += lg[k];
+      if (suf >= lo_c && suf <= hi_c && (c < 0 || std::abs(2 * suf - s) < std::abs(2 * c - s))) c = suf;
+    }
+  }
+  if (c < 0) c = std::min(hi_c, std::max(lo_c, (s + 1) / 2));
+  std::vector<Digit> rev;
+  int acc = 0, first_trailing = -1;
+  bool split = false;
+  for (int j = n - 1; j >= 0; --j) {
+    if (acc < c && acc + lg[j] > c) {
+      const int lob = c - acc, hib = lg[j] - lob;
+      rev.push_back(Digit{j, i64(1) << lob, 2, 1, i64(1) << hib});
+      rev.push_back(Digit{j, i64(1) << hib, 1, i64(1) << lob, 1});
+      split = true;
+    } else {
+      rev.push_back(Digit{j, p->eps[j], 0, 1, 1});
+    }
+    acc += lg[j];
+  }
+  p->digits.assign(rev.rbegin(), rev.rend());
+  const int D = (int)p->digits.size();
+  // first digit of the trailing chunk
+  int bits = 0;
+  for (int g = D - 1; g >= 0; --g) {
+    bits += ilog2(p->digits[g].n);
+    if (bits == c) {
+      first_trailing = g;
+      break;
+    }
+  }
+  if (first_trailing <= 0) throw StatusError{E_STATE};
+  const PassRange lead{0, first_trailing, split, 0};
+  const PassRange trail{first_trailing, D, false, 0};
+  if (split || (p->order & 1)) {
+    p->ranges.push_back(lead);
+    p->ranges.push_back(trail);
+  } else {
+    p->ranges.push_back(trail);
+    p->ranges.push_back(lead);
+  }
+}
+
 void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& out_side, int sign,
                   TwCache& tw) {
   E.sign = sign;
@@ -262,7 +335,13 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
     // register-resident kernel for power-of-two pencils of at least 32 points
     bool pow2 = pd.L >= 32 && pd.L <= kMaxPencil && (p->m < (i64(1) << 30));
     for (int g = R.a; g < R.b; ++g) pow2 = pow2 && is_pow2(dg[g].n);
-    if (pow2) {
+    if (p->tile_lg > 0) {
+      // fixed tiles of 2^tile_lg elements (the schedule guarantees the shapes)
+      pd.kind = 1;
+      pd.P = 16;
+      pd.W = (int)((i64(1) << p->tile_lg) / pd.L);
+      pd.split = 0;
+    } else if (pow2) {
       pd.kind = 1;
       if (pd.S == 1) {
         pd.P = 16;
@@ -283,6 +362,7 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
       int stride = (int)range_count(dg, g + 1, R.b);
       i64 Ns = 1;
       std::vector<int> rads = pd.kind == 1 ? pow2_radices(dg[g].n) : radices_of(dg[g].n);
+      if (pd.kind == 1 && (p->order & 2)) std::reverse(rads.begin(), rads.end());
       for (int r : rads) {
         if (pd.nst >= kMaxStages) throw StatusError{E_UNSUPPORTED};
         StageDesc& s = pd.st[pd.nst++];
@@ -302,11 +382,14 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
     pd.scale = (pi == np - 1) ? (float)(1.0 / std::sqrt((double)p->m)) : 1.0f;
     pd.post = R.post ? 1 : 0;
     if (R.post) {
-      // this pass is the high digit a; the low digit is a + 1
-      i64 N = dg[R.a].n * dg[R.a + 1].n;
+      // the high digit closes this pass (digit b - 1); the low digit is b
+      const int hi = R.b - 1, lo = R.b;
+      if (dg[hi].part != 1 || lo >= D || dg[lo].part != 2) throw StatusError{E_STATE};
+      i64 N = dg[hi].n * dg[lo].n;
       pd.postN = (int)N;
-      pd.lo_n = (int)dg[R.a + 1].n;
-      pd.lo_div = (int)range_count(dg, R.a + 2, D);
+      pd.post_lmod = (int)dg[hi].n;
+      pd.lo_n = (int)dg[lo].n;
+      pd.lo_div = (int)range_count(dg, lo + 1, D);
       auto pr = tw.twolevel(N);
       pd.tw_hi = pr.first;
       pd.tw_lo = pr.second;
@@ -379,7 +462,8 @@ size_t Blob::add(const void* p, size_t n) {
   return off;
 }
 
-LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags) {
+LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags, int tile_lg,
+                                int order) {
   if (d < 1 || d > kMaxD || !Mrm || batch < 1) throw StatusError{E_ARG};
   auto* p = new LatticePlan();
   try {
@@ -387,6 +471,9 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
     p->M = Mat::from(d, Mrm);
     p->batch = batch;
     p->flags = flags;
+    p->tile_lg = tile_lg;
+    p->order = order;
+    if (tile_lg != 0 && (tile_lg < 8 || tile_lg > 13)) throw StatusError{E_ARG};
     i64 D = det(p->M);
     if (D == 0) throw StatusError{E_SINGULAR};
     p->m = D < 0 ? -D : D;
@@ -401,7 +488,9 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
     for (int i = 0; i < d; ++i)
       if (p->Sf.eps[i] > 1) p->eps.push_back(p->Sf.eps[i]);
     // digits
-    if (p->eps.empty()) {
+    if (tile_lg > 0) {
+      tiled_schedule(p);
+    } else if (p->eps.empty()) {
       p->digits.push_back(Digit{0, 1, 0, 1, 1});
     } else {
       for (int j = 0; j < (int)p->eps.size(); ++j) {
@@ -424,7 +513,9 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       }
     }
     const int Dg = (int)p->digits.size();
-    if (p->m <= kMaxTile) {
+    if (tile_lg > 0) {
+      // ranges set by the tiled schedule
+    } else if (p->m <= kMaxTile) {
       p->ranges.push_back(PassRange{0, Dg, false, 0});
     } else {
       int i = Dg - 1;

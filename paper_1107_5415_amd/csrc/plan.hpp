@@ -76,6 +76,8 @@ struct LatticePlan {
   i64 m = 0;
   i64 batch = 1;
   uint32_t flags = 0;
+  int tile_lg = 0;          // fixed-tile schedule (0: default schedule)
+  int order = 0;
   Smith Sf;                 // forward basis (largest cycle along sample key e_d)
   Smith Si;                 // basis of M^T used by the natural->natural inverse
   bool Sf_aligned = false, Si_aligned = false;
@@ -89,7 +91,12 @@ struct LatticePlan {
   size_t ws_elems = 0;      // workspace (complex64 elements) per call
 };
 
-LatticePlan* build_lattice_plan(int d, const i64* M, i64 batch, uint32_t flags);
+// tile_lg > 0 selects the fixed-tile schedule of the batched launch (tiles of
+// 2^tile_lg elements, 8 <= tile_lg <= 13); order bit 0: leading chunk first,
+// bit 1: smallest radix first, bit 2: chunk boundary mid-axis even where an
+// axis boundary fits.
+LatticePlan* build_lattice_plan(int d, const i64* M, i64 batch, uint32_t flags, int tile_lg = 0,
+                                int order = 0);
 void upload_plan(LatticePlan* p);   // allocates device tables (throws StatusError)
 void free_plan(LatticePlan* p);
 

@@ -31,8 +31,14 @@ EXPORTS = [
     "lwt_plan_create", "lwt_plan_destroy", "lwt_level_info", "lwt_dirichlet_mask",
     "lwt_workspace_size", "lwt_saved_elems", "lwt_decompose", "lwt_reconstruct",
     "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_trace_begin", "lfft_trace_end",
-    "lfft_trace_get", "lfft_strerror",
+    "lfft_trace_get", "lfft_strerror", "lfft_batch_create", "lfft_batch_destroy",
+    "lfft_batch_offsets", "lfft_batch_workspace_size", "lfft_batch_configure", "lfft_batch_config",
+    "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute", "lfft_batch_status",
 ]
+
+LFFT_BATCH_LOOP = 0
+LFFT_BATCH_PERSISTENT = 1
+LFFT_BATCH_GRAPH = 2
 
 _lib = None
 _lock = threading.Lock()
@@ -83,6 +89,16 @@ def lib():
             "lfft_trace_get": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                               ctypes.POINTER(ctypes.c_double), _FP]),
             "lfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "lfft_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, _I64P, ctypes.c_uint32]),
+            "lfft_batch_destroy": (ctypes.c_int, [_P]),
+            "lfft_batch_offsets": (ctypes.c_int, [_P, _I64P]),
+            "lfft_batch_workspace_size": (ctypes.c_size_t, [_P]),
+            "lfft_batch_configure": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+            "lfft_batch_config": (ctypes.c_int, [_P, _I32P, _I32P, _I32P]),
+            "lfft_batch_schedule": (ctypes.c_int, [_P, ctypes.c_int, _I32P, _I64P, _I64P, _I32P]),
+            "lfft_batch_tune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _FP, _P]),
+            "lfft_batch_execute": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
+            "lfft_batch_status": (ctypes.c_int, [_P, _I32P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -370,6 +386,99 @@ class WaveletPlan:
                                               _dptr(ws), _stream_handle(g.device)),
                "lwt_reconstruct_backward")
         return gc
+
+
+class BatchPlan:
+    """Lattice FFTs of signals on patterns of different M in one call
+    (lfft_batch_*).  Signals are concatenated: signal i occupies elements
+    offsets[i]:offsets[i+1] of a complex64 device tensor."""
+
+    def __init__(self, Ms, host_only=False):
+        Ms = [_mat(M) for M in Ms]
+        if not Ms:
+            raise ValueError("at least one matrix expected")
+        self.d = Ms[0].shape[0]
+        if any(M.shape != (self.d, self.d) for M in Ms):
+            raise ValueError("all matrices must have the same dimension")
+        self.count = len(Ms)
+        self.Ms = np.ascontiguousarray(np.stack(Ms))
+        h = _P()
+        _check(lib().lfft_batch_create(ctypes.byref(h), self.count, self.d, _ptr64(self.Ms),
+                                       LFFT_HOST_ONLY if host_only else 0), "lfft_batch_create")
+        self._h = h
+        self._ws = None
+        off = np.zeros(self.count + 1, np.int64)
+        _check(lib().lfft_batch_offsets(self._h, _ptr64(off)), "lfft_batch_offsets")
+        self.offsets = off
+        self.total = int(off[-1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lfft_batch_destroy(h)
+            self._h = None
+
+    def configure(self, tile_lg, order=0):
+        _check(lib().lfft_batch_configure(self._h, int(tile_lg), int(order)), "lfft_batch_configure")
+
+    def config(self):
+        t = ctypes.c_int()
+        o = ctypes.c_int()
+        e = ctypes.c_int()
+        _check(lib().lfft_batch_config(self._h, ctypes.byref(t), ctypes.byref(o), ctypes.byref(e)),
+               "lfft_batch_config")
+        return dict(tile_lg=t.value, order=o.value, eligible=e.value)
+
+    def schedule(self, i):
+        n = ctypes.c_int()
+        L = np.zeros(2, np.int64)
+        T = np.zeros(2, np.int64)
+        post = (ctypes.c_int * 2)()
+        _check(lib().lfft_batch_schedule(self._h, int(i), ctypes.byref(n), _ptr64(L), _ptr64(T),
+                                         ctypes.cast(post, _I32P)), "lfft_batch_schedule")
+        k = n.value
+        return dict(passes=k, pencil=L[:k].tolist(), tiles=T[:k].tolist(), post=list(post)[:k])
+
+    def _workspace(self, device):
+        torch = _torch()
+        nb = int(lib().lfft_batch_workspace_size(self._h))
+        if self._ws is None or self._ws.device != device:
+            self._ws = torch.empty(max(nb // 8, 1), dtype=torch.complex64, device=device)
+        return self._ws
+
+    def _check_signal(self, x):
+        torch = _torch()
+        if not x.is_cuda or x.dtype != torch.complex64 or x.numel() != self.total:
+            raise RuntimeError("complex64 device tensor of %d elements expected" % self.total)
+        return x.contiguous()
+
+    def execute(self, x, inverse=False, mode=LFFT_BATCH_GRAPH, out=None):
+        torch = _torch()
+        x = self._check_signal(x)
+        if out is None:
+            out = torch.empty_like(x)
+        ws = self._workspace(x.device)
+        _check(lib().lfft_batch_execute(self._h, 1 if inverse else 0, int(mode), _dptr(x), _dptr(out),
+                                        _dptr(ws), _stream_handle(x.device)), "lfft_batch_execute")
+        return out
+
+    def tune(self, x, reps=3, out=None):
+        """Autotune on x (overwrites out); returns the best time in ms (-1 if
+        the choice was already known for these matrices)."""
+        torch = _torch()
+        x = self._check_signal(x)
+        if out is None:
+            out = torch.empty_like(x)
+        ws = self._workspace(x.device)
+        best = ctypes.c_float()
+        _check(lib().lfft_batch_tune(self._h, _dptr(x), _dptr(out), _dptr(ws), int(reps),
+                                     ctypes.byref(best), _stream_handle(x.device)), "lfft_batch_tune")
+        return best.value
+
+    def status(self):
+        e = ctypes.c_int()
+        _check(lib().lfft_batch_status(self._h, ctypes.byref(e)), "lfft_batch_status")
+        return e.value
 
 
 def trace_begin(capacity=100000):

@@ -204,3 +204,66 @@ def test_error_codes():
     assert lib.lfft_forward(p._h, ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf2, ctypes.c_void_p),
                             None, 0x10, None) == -1
     assert lfft.strerror(-3).startswith("J^{-1} M")
+
+
+def _suffix_bits(eps):
+    """log2 sums of the trailing non-trivial elementary divisors (axis boundaries)."""
+    lg = [int(e).bit_length() - 1 for e in eps]
+    return [sum(lg[k:]) for k in range(1, len(lg))], sum(lg)
+
+
+def test_batch_schedules():
+    """Fixed-tile schedules of the batched launch: every pass is a power-of-two
+    pencil of 32..2^tile_lg points filling whole tiles, the pencils of a
+    lattice multiply to m, the four-step twiddle only follows the first of
+    two passes, and an axis boundary is used whenever one fits."""
+    Ms = workloads.batched_matrices()[:96] + [((1, 0), (0, 1 << 18)), ((1 << 18, 0), (0, 1)),
+                                             ((32, 0), (0, 32)), ((2, 1), (0, 1 << 13)),
+                                             ((32, 8), (-8, 32)), ((3, 0), (0, 1024))]
+    b = lfft.BatchPlan(Ms, host_only=True)
+    ms = [abs(L.det(M)) for M in Ms]
+    assert b.offsets.tolist() == np.concatenate([[0], np.cumsum(ms)]).tolist()
+    for tl in (11, 12, 13):
+        for order in range(8):
+            b.configure(tl, order)
+            cfg = b.config()
+            assert (cfg["tile_lg"], cfg["order"]) == (tl, order)
+            n_elig = 0
+            for i, M in enumerate(Ms):
+                eps = [e for e in L.elementary_divisors(M) if e > 1]
+                pow2 = all(e & (e - 1) == 0 for e in eps)
+                s = sch = b.schedule(i)
+                if not pow2:
+                    assert sch["passes"] == 0
+                    continue
+                n_elig += 1
+                m = ms[i]
+                assert sch["passes"] == (1 if m <= (1 << tl) else 2)
+                assert int(np.prod(sch["pencil"])) == m
+                for Lp, T in zip(s["pencil"], s["tiles"]):
+                    assert Lp & (Lp - 1) == 0 and 32 <= Lp <= (1 << tl)
+                    assert T == max(1, m // (1 << tl))
+                if sch["passes"] == 2:
+                    assert sch["post"][1] == 0
+                    bounds, total = _suffix_bits(eps)
+                    fits = [c for c in bounds if max(5, total - tl) <= c <= min(tl, total - 5)]
+                    if fits and not (order & 4):
+                        assert sch["post"][0] == 0
+                    if not fits:
+                        assert sch["post"][0] == 1
+                else:
+                    assert sch["post"] == [0]
+            assert cfg["eligible"] == n_elig
+    assert _err(lambda: b.configure(10, 0)) == -1
+    assert _err(lambda: b.configure(12, 8)) == -1
+    lib = lfft.lib()
+    buf = (ctypes.c_float * 64)()
+    buf2 = (ctypes.c_float * 64)()
+    args = [ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf2, ctypes.c_void_p),
+            ctypes.cast(buf2, ctypes.c_void_p)]
+    assert lib.lfft_batch_execute(b._h, 0, 1, args[0], args[1], args[0], None) == -8
+    assert lib.lfft_batch_execute(b._h, 0, 7, args[0], args[1], args[0], None) == -1
+    assert lib.lfft_batch_execute(b._h, 0, 1, args[0], args[0], args[1], None) == -1
+    e = ctypes.c_int()
+    assert lib.lfft_batch_status(b._h, ctypes.byref(e)) == -8
+    assert _err(lambda: lfft.BatchPlan([((1, 2), (2, 4))], host_only=True)) == -2
