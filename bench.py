@@ -94,12 +94,95 @@ def cpu_baseline(cfg, m, levels):
                        % (os.cpu_count(), dt))
 
 
+def _time_ms(fn, reps, torch):
+    """Mean ms of fn() over reps runs, HIP events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def variant_batched(torch, lfft, reps):
+    """512 lattices [[2^a, c], [0, 2^b]] (a + b in 10..18), concatenated
+    complex64 signals: per-lattice launches vs the persistent launch vs its
+    captured graph, after autotuning."""
+    import workloads
+    seed = workloads.CONFIGS["batched"]["seed"]
+    Ms = workloads.batched_matrices(seed=seed)
+    plan = lfft.BatchPlan(Ms)
+    x = torch.from_numpy(workloads.complex_normal(seed, plan.total)).cuda()
+    y = torch.empty_like(x)
+    t0 = time.perf_counter()
+    plan.tune(x, reps=3, out=y)
+    tune_s = time.perf_counter() - t0
+    off = [int(v) for v in plan.offsets]
+    ms = [off[i + 1] - off[i] for i in range(len(Ms))]
+    flops = sum(fft_flops(mi) for mi in ms)
+    res = {}
+    for name, mode in (("loop", 0), ("persistent", 1), ("graph", 2)):
+        t = _time_ms(lambda: plan.execute(x, mode=mode, out=y), reps, torch)
+        res[name] = {"ms": round(t, 4), "gflops": round(flops / (t / 1e3) / 1e9, 1),
+                     "alg_gbs": round(16.0 * plan.total / (t / 1e3) / 1e9, 1)}
+    return {"workload": "512 lattices M=[[2^a,c],[0,2^b]], a+b uniform in 10..18, seed %d, "
+                        "sum m_i = %d complex64, forward FFT natural order" % (seed, plan.total),
+            "config": plan.config(), "tune_s": round(tune_s, 2), **res,
+            "graph_vs_loop": round(res["loop"]["ms"] / res["graph"]["ms"], 2)}
+
+
+def variant_grad(torch, lfft, reps):
+    """Differentiation workload: M = [[1024, 256], [0, 1024]] (m = 2^20),
+    batch 16, 4 quincunx levels; loss = sum_l ||d2_l||^2 + ||S(D(x)) - t||^2;
+    forward only vs forward + hand-written adjoint backward."""
+    import workloads
+    from paper_1107_5415_amd import autograd as AG
+    cfg = workloads.CONFIGS["grad"]
+    B, m = cfg["batch"], 1 << 20
+    plan = lfft.WaveletPlan(cfg["M"], cfg["J"], cfg["levels"], batch=B)
+    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], (B, m))).cuda().requires_grad_(True)
+    tgt = torch.from_numpy(workloads.complex_normal(cfg["target_seed"], (B, m))).cuda()
+    masks = [mk.requires_grad_(True) for mk in plan.dirichlet_masks(torch.device("cuda:0"))]
+    blocks = AG.channel_blocks(plan)[:-1]
+
+    def loss_fn():
+        c = AG.wavelet_decompose(x, plan, masks)
+        loss = 0.0
+        for off, n in blocks:
+            blk = c[:, off:off + n]
+            loss = loss + torch.sum(blk.real ** 2 + blk.imag ** 2)
+        r = AG.wavelet_reconstruct(c, plan, masks) - tgt
+        return loss + torch.sum(r.real ** 2 + r.imag ** 2)
+
+    def fwd():
+        with torch.no_grad():
+            loss_fn()
+
+    def fwd_bwd():
+        x.grad = None
+        for mk in masks:
+            mk.grad = None
+        loss_fn().backward()
+
+    tf = _time_ms(fwd, reps, torch)
+    tb = _time_ms(fwd_bwd, reps, torch)
+    return {"workload": "M=[[1024,256],[0,1024]] m=2^20, batch 16, 4 quincunx levels, "
+                        "gradients wrt samples and the 4 FP32 masks",
+            "forward_ms": round(tf, 3), "forward_backward_ms": round(tb, 3),
+            "backward_over_forward": round((tb - tf) / tf, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the lattice FFT/wavelet hot path runs on a single "
@@ -211,6 +294,10 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phase.items()},
         "kernels": kernels,
     }
+    if not args.no_variants:
+        log("bench: variants (batched, differentiation)")
+        out["variants"] = {"batched": variant_batched(torch, lfft, max(5, args.steps // 2)),
+                           "grad": variant_grad(torch, lfft, max(3, args.steps // 4))}
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host (one step)")
         out["cpu_baseline"] = cpu_baseline(cfg, m, levels)

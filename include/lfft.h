@@ -188,16 +188,18 @@ int lwt_reconstruct_backward(lwt_plan_t plan, const void* grad_samples, const vo
  * (each d x d, row-major, stored one after another in Ms) are concatenated,
  * signal i holding m_i = |det M_i| complex64 values at element offset
  * offsets[i] = m_0 + ... + m_{i-1}.  Every lattice is transformed
- * independently (Section 4.2: the blocks of the Kronecker form are
- * independent), natural order in and out, with the unitary transform of
- * lfft_forward / lfft_inverse.  The plan holds, for the configuration in
+ * independently, natural order in and out, with the unitary transform of
+ * lfft_forward / lfft_inverse.  Within one pass the pencils act on disjoint
+ * blocks of the data (Section 4.2, the remark after Theorem 2), so the tiles
+ * of the same pass of all lattices share one launch.  The plan holds, for the configuration in
  * use, a fixed-tile schedule of every lattice whose elementary divisors are
  * powers of two and 32 <= m_i <= 2^(2 tile_lg); other lattices run through
  * their own lfft plan after the batched launch. */
 typedef struct lfft_batch_s* lfft_batch_t;
 
 #define LFFT_BATCH_LOOP 0        /* one lfft launch sequence per lattice      */
-#define LFFT_BATCH_PERSISTENT 1  /* one persistent kernel over all lattices   */
+#define LFFT_BATCH_PERSISTENT 1  /* two persistent launches over all lattices:
+                                    every first pass, then every second pass */
 #define LFFT_BATCH_GRAPH 2       /* the persistent launch as a HIP graph,
                                     captured on first use for each (direction,
                                     in, out, workspace) and replayed after    */
@@ -244,15 +246,10 @@ int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspac
 
 /* out = F(M_i) in (inverse != 0: F(M_i)^{-1}) for every lattice, in device
  * complex64 [sum m_i], out of place, on `stream`.  mode: LFFT_BATCH_*.
- * Calls on one plan must not overlap in time (they share the queue heads
- * and counters).  Errors: ARG, STATE (host-only plan), HIP. */
+ * Calls on one plan must not overlap in time (they share the queue heads).
+ * Errors: ARG, STATE (host-only plan), HIP. */
 int lfft_batch_execute(lfft_batch_t plan, int inverse, int mode, const void* in, void* out,
                        void* workspace, hipStream_t stream);
-
-/* Error flag of the persistent launch: non-zero if a dependency wait ever
- * exceeded its spin limit (the results of that call are then invalid).
- * Synchronises the device and clears the flag. */
-int lfft_batch_status(lfft_batch_t plan, int* error_flag);
 
 /* ---- per-launch kernel timing (tracing) -------------------------------- */
 

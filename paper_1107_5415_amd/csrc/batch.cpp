@@ -56,11 +56,13 @@ void* upload(const std::vector<T>& v) {
   return d;
 }
 
-// Fill the eight XCD queues of one direction.
+// Fill the eight XCD queues of both phases of one direction: phase 0 holds
+// the first pass of every lattice, phase 1 the second pass of the lattices
+// that need two.  Lattices go to queues by longest-processing-time
+// assignment, largest first inside a queue.
 void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
   std::vector<BatchPass> passes;
   struct Inst {
-    int idx;
     int first;      // index of its first BatchPass
     int np;
     i64 work;
@@ -72,7 +74,7 @@ void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
     const Engine& E = inverse ? p->inv_nat : p->fwd;
     const int np = (int)E.passes.size();
     if (np < 1 || np > 2) throw StatusError{E_STATE};
-    Inst in{i, (int)passes.size(), np, b->m[i] * np};
+    Inst in{(int)passes.size(), np, b->m[i]};
     for (int k = 0; k < np; ++k) {
       BatchPass bp{};
       bp.pd = E.passes[k];
@@ -95,15 +97,11 @@ void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
       bp.out_off = b->off[i];
       bp.in_buf = first ? 0 : 2;
       bp.out_buf = last ? 1 : 2;
-      bp.inst = i;
-      bp.need = (k == 1) ? (int)pass_tiles(E.passes[0]) : 0;
-      bp.signal = (np == 2 && k == 0) ? 1 : 0;
       bp.variant = variant_of(bp.pd, first, last);
       passes.push_back(bp);
     }
     insts.push_back(in);
   }
-  // longest-processing-time assignment of lattices to the 8 queues
   std::vector<int> order(insts.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
@@ -115,42 +113,29 @@ void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
     q[best].push_back(k);
     load[best] += insts[k].work;
   }
-  // items: a lattice's second pass is emitted once at least `lag` items have
-  // followed the end of its first pass (one wave of the XCD's workgroups)
-  const i64 lag = std::max(1, b->grid / 8);
   std::vector<int2> items;
-  std::vector<int> qbeg(9, 0);
-  for (int x = 0; x < 8; ++x) {
-    qbeg[x] = (int)items.size();
-    struct Pending {
-      int inst;
-      i64 end;
-    };
-    std::vector<Pending> pend;
-    size_t head = 0;
-    auto emit_second = [&](const Inst& I) {
-      const int pi = I.first + 1;
-      const i64 nt = pass_tiles(passes[pi].pd);
-      for (i64 t = 0; t < nt; ++t) items.push_back(make_int2(pi, (int)t));
-    };
-    for (int k : q[x]) {
-      const Inst& I = insts[k];
-      const i64 nt = pass_tiles(passes[I.first].pd);
-      for (i64 t = 0; t < nt; ++t) items.push_back(make_int2(I.first, (int)t));
-      if (I.np == 2) pend.push_back(Pending{k, (i64)items.size()});
-      while (head < pend.size() && (i64)items.size() - pend[head].end >= lag)
-        emit_second(insts[pend[head++].inst]);
+  std::vector<int> qbeg(17, 0);
+  for (int ph = 0; ph < 2; ++ph) {
+    for (int x = 0; x < 8; ++x) {
+      qbeg[8 * ph + x] = (int)items.size();
+      for (int k : q[x]) {
+        const Inst& I = insts[k];
+        if (ph >= I.np) continue;
+        const int pi = I.first + ph;
+        const i64 nt = pass_tiles(passes[pi].pd);
+        for (i64 t = 0; t < nt; ++t) items.push_back(make_int2(pi, (int)t));
+      }
     }
-    while (head < pend.size()) emit_second(insts[pend[head++].inst]);
+    D.phase_items[ph] = (int)items.size() - qbeg[8 * ph];
   }
-  qbeg[8] = (int)items.size();
+  qbeg[16] = (int)items.size();
   if (items.size() > (size_t)0x7fffffff) throw StatusError{E_UNSUPPORTED};
   D.npass = (int)passes.size();
   D.nitems = (int)items.size();
   D.dpass = upload(passes);
-  std::vector<uint8_t> blob(items.size() * sizeof(int2) + 9 * sizeof(int));
+  std::vector<uint8_t> blob(items.size() * sizeof(int2) + 17 * sizeof(int));
   std::memcpy(blob.data(), items.data(), items.size() * sizeof(int2));
-  std::memcpy(blob.data() + items.size() * sizeof(int2), qbeg.data(), 9 * sizeof(int));
+  std::memcpy(blob.data() + items.size() * sizeof(int2), qbeg.data(), 17 * sizeof(int));
   D.ditems = upload(blob);
   D.qbeg = reinterpret_cast<const int*>(static_cast<uint8_t*>(D.ditems) + items.size() * sizeof(int2));
 }
@@ -173,17 +158,22 @@ void enqueue_persistent(BatchPlan* b, bool inverse, const void* in, void* out, v
                         hipStream_t s, bool trace) {
   const BatchDir& D = b->dir[inverse ? 1 : 0];
   if (D.nitems > 0) {
-    hipError_t e = launch_batch_clear(b->dctl, b->dctl + 16, b->count, s);
+    hipError_t e = launch_batch_clear(b->dheads, 16, s);
     if (e != hipSuccess) throw StatusError{E_HIP};
-    double bytes = 0;
-    for (int i = 0; i < b->count; ++i)
-      if (b->tiled[i]) bytes += 16.0 * (double)b->m[i];
-    TraceScope ts(trace && trace_on() ? batch_kernel_name(b->tile_lg) : nullptr, bytes, s);
-    e = launch_batch(b->tile_lg, static_cast<const BatchPass*>(D.dpass),
-                     static_cast<const int2*>(D.ditems), D.qbeg, b->dctl, b->dctl + 16,
-                     static_cast<const float2*>(in), static_cast<float2*>(out),
-                     static_cast<float2*>(ws), b->spin_limit, b->grid, s);
-    if (e != hipSuccess) throw StatusError{E_HIP};
+    for (int ph = 0; ph < 2; ++ph) {
+      if (D.phase_items[ph] == 0) continue;
+      double bytes = 0;
+      for (int i = 0; i < b->count; ++i) {
+        const LatticePlan* p = b->tiled[i];
+        if (p && (int)p->fwd.passes.size() > ph) bytes += 16.0 * (double)b->m[i];
+      }
+      TraceScope ts(trace && trace_on() ? batch_kernel_name(b->tile_lg) : nullptr, bytes, s);
+      e = launch_batch(b->tile_lg, static_cast<const BatchPass*>(D.dpass),
+                       static_cast<const int2*>(D.ditems), D.qbeg + 8 * ph, b->dheads + 8 * ph,
+                       static_cast<const float2*>(in), static_cast<float2*>(out),
+                       static_cast<float2*>(ws), b->grid, s);
+      if (e != hipSuccess) throw StatusError{E_HIP};
+    }
   }
   // lattices the fixed-tile schedule does not cover: one plan each
   for (int i = 0; i < b->count; ++i) {
@@ -227,9 +217,9 @@ BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags) {
     b->single.assign(count, nullptr);
     b->ws_elems = (size_t)b->total;
     if (!(flags & 1)) {
-      const size_t n = (16 + (size_t)count) * sizeof(int);
-      if (hipMalloc(&b->dctl, n) != hipSuccess) throw StatusError{E_NOMEM};
-      if (hipMemset(b->dctl, 0, n) != hipSuccess) throw StatusError{E_HIP};
+      const size_t n = 16 * sizeof(int);
+      if (hipMalloc(&b->dheads, n) != hipSuccess) throw StatusError{E_NOMEM};
+      if (hipMemset(b->dheads, 0, n) != hipSuccess) throw StatusError{E_HIP};
       if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
         throw StatusError{E_HIP};
     }
@@ -245,7 +235,7 @@ void free_batch_plan(BatchPlan* b) {
   if (!b) return;
   drop_tiled(b);
   for (auto* p : b->single) free_plan(p);
-  if (b->dctl) (void)hipFree(b->dctl);
+  if (b->dheads) (void)hipFree(b->dheads);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
@@ -286,7 +276,7 @@ void configure_batch(BatchPlan* b, int tile_lg, int order) {
 
 void exec_batch(BatchPlan* b, bool inverse, int mode, const void* in, void* out, void* ws,
                 hipStream_t s) {
-  if (!b->configured || !b->dctl) throw StatusError{E_STATE};
+  if (!b->configured || !b->dheads) throw StatusError{E_STATE};
   if (mode == BATCH_LOOP) {
     for (int i = 0; i < b->count; ++i) {
       LatticePlan* p = single_plan(b, i);
@@ -331,7 +321,7 @@ void exec_batch(BatchPlan* b, bool inverse, int mode, const void* in, void* out,
 
 void tune_batch(BatchPlan* b, const void* in, void* out, void* ws, int reps, hipStream_t s,
                 float* best_ms) {
-  if (!b->dctl || reps < 1) throw StatusError{E_ARG};
+  if (!b->dheads || reps < 1) throw StatusError{E_ARG};
   TuneKey key{b->d, b->Ms};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -363,7 +353,6 @@ void tune_batch(BatchPlan* b, const void* in, void* out, void* ws, int reps, hip
           (void)hipEventElapsedTime(&ms, e0, e1);
           if (tmin < 0 || ms < tmin) tmin = ms;
         }
-        if (batch_error_flag(b, true) != 0) continue;
         if (best < 0 || tmin < best) {
           best = tmin;
           arg = {tl, ord};
@@ -383,20 +372,6 @@ void tune_batch(BatchPlan* b, const void* in, void* out, void* ws, int reps, hip
     g_tune_cache[key] = arg;
   }
   if (best_ms) *best_ms = best;
-}
-
-int batch_error_flag(BatchPlan* b, bool clear) {
-  if (!b->dctl) throw StatusError{E_STATE};
-  int v = 0;
-  if (hipDeviceSynchronize() != hipSuccess) throw StatusError{E_HIP};
-  if (hipMemcpy(&v, b->dctl + 8, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-    throw StatusError{E_HIP};
-  if (clear && v) {
-    int z = 0;
-    if (hipMemcpy(b->dctl + 8, &z, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
-      throw StatusError{E_HIP};
-  }
-  return v;
 }
 
 }  // namespace lfft

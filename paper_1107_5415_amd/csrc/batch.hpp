@@ -1,6 +1,6 @@
 // Host side of the batched lattice FFT: many signals on patterns of
-// different M, executed by per-lattice launches, by one persistent launch,
-// or by a captured graph of that launch; plus the autotuner that picks the
+// different M, executed by per-lattice launches, by the two-phase persistent
+// launch, or by a captured graph of it; plus the autotuner that picks the
 // tile size and the pass/radix order.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -18,9 +18,10 @@ enum BatchMode : int { BATCH_LOOP = 0, BATCH_PERSISTENT = 1, BATCH_GRAPH = 2 };
 
 struct BatchDir {
   void* dpass = nullptr;      // BatchPass[npass]
-  void* ditems = nullptr;     // int2[nitems] followed by qbeg[9]
+  void* ditems = nullptr;     // int2[nitems] followed by qbeg[17]
   int npass = 0, nitems = 0;
-  const int* qbeg = nullptr;  // device pointer inside ditems
+  int phase_items[2] = {0, 0};
+  const int* qbeg = nullptr;  // device: queue x of phase p is [qbeg[8p + x], qbeg[8p + x + 1])
 };
 
 struct BatchPlan {
@@ -35,9 +36,8 @@ struct BatchPlan {
   std::vector<LatticePlan*> single;     // default plans, built on first per-lattice use
   int eligible = 0;
   BatchDir dir[2];                      // forward, inverse
-  int* dctl = nullptr;                  // 16 control ints followed by count counters
+  int* dheads = nullptr;                // 16 queue heads (8 per phase)
   int grid = 0;
-  int spin_limit = 1 << 22;
   hipStream_t cap = nullptr;            // private stream for graph capture
   std::map<std::tuple<int, const void*, void*, void*>, hipGraphExec_t> graphs;
   size_t ws_elems = 0;
@@ -53,6 +53,5 @@ void exec_batch(BatchPlan* b, bool inverse, int mode, const void* in, void* out,
 // mode) and keeps the fastest; results are cached per set of matrices.
 void tune_batch(BatchPlan* b, const void* in, void* out, void* ws, int reps, hipStream_t s,
                 float* best_ms);
-int batch_error_flag(BatchPlan* b, bool clear);
 
 }  // namespace lfft

@@ -324,7 +324,7 @@ int lfft_batch_schedule(lfft_batch_t plan, int i, int* passes, int64_t* pencil, 
 int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspace, int reps,
                     float* best_ms, hipStream_t stream) {
   if (!plan || !in || !out || in == out || !workspace || reps < 1) return LFFT_E_ARG;
-  if (!plan->b->dctl) return LFFT_E_STATE;
+  if (!plan->b->dheads) return LFFT_E_STATE;
   return guarded([&] { lfft::tune_batch(plan->b, in, out, workspace, reps, stream, best_ms); });
 }
 
@@ -332,14 +332,8 @@ int lfft_batch_execute(lfft_batch_t plan, int inverse, int mode, const void* in,
                        void* workspace, hipStream_t stream) {
   if (!plan || !in || !out || in == out || !workspace) return LFFT_E_ARG;
   if (mode < LFFT_BATCH_LOOP || mode > LFFT_BATCH_GRAPH) return LFFT_E_ARG;
-  if (!plan->b->dctl) return LFFT_E_STATE;
+  if (!plan->b->dheads) return LFFT_E_STATE;
   return guarded([&] { lfft::exec_batch(plan->b, inverse != 0, mode, in, out, workspace, stream); });
-}
-
-int lfft_batch_status(lfft_batch_t plan, int* error_flag) {
-  if (!plan || !error_flag) return LFFT_E_ARG;
-  if (!plan->b->dctl) return LFFT_E_STATE;
-  return guarded([&] { *error_flag = lfft::batch_error_flag(plan->b, true); });
 }
 
 const char* lfft_strerror(int status) {

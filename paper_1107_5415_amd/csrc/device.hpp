@@ -74,9 +74,6 @@ struct BatchPass {
   PassDesc pd;                // batch 1, maps and batch strides resolved
   long long in_off, out_off;  // element offsets of the lattice's signal
   int in_buf, out_buf;
-  int inst;                   // dependency counter of the lattice
-  int need;                   // finished tiles of its first pass required first (0: none)
-  int signal;                 // 1: count every finished tile in the counter
   int variant;                // body: BATCH_ROWS_NN .. BATCH_COLS_IN
 };
 

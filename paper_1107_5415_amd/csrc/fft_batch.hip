@@ -1,19 +1,16 @@
 // Batched persistent launch: the lattice FFTs of many signals on patterns of
-// different M in one kernel.  Every pass of every lattice is cut into tiles
-// of T elements, each processed by T / 16 threads with the register-resident
-// pass body of fast_tile.hpp;
-// the tiles form eight work queues, one per XCD, that the host fills so that
-// each lattice stays on one XCD and its second pass follows its first pass
-// by at least one wave of workgroups.
+// different M.  Every pass of every lattice is cut into tiles of T elements,
+// each processed by T / 16 threads with the register-resident pass body of
+// fast_tile.hpp.  The tiles of all first passes (and of lattices done in one
+// pass) form phase 0, the tiles of all second passes phase 1; each phase is
+// one persistent launch over eight work queues, one per XCD, that the host
+// fills largest lattice first so that a lattice's tiles stay on one XCD.
+// The kernel boundary between the phases orders the two passes of every
+// lattice, so the tiles need no counters, fences or waits.
 //
 // A workgroup takes items from the queue of its own XCD (dispatch index
-// mod 8) and then from the others.  The second pass of a lattice waits until
-// a counter shows that every tile of its first pass is done; the items are
-// claimed in queue order, so every item waited for has already been claimed
-// by a running workgroup that never waits for a later item, and the wait
-// always ends.  The wait is still bounded: past the spin limit it records
-// an error flag and goes on, so a wrong schedule gives a reported error, not
-// a hang.
+// mod 8) and, once that is empty, from the others; it exits when all eight
+// are empty.
 #include <hip/hip_runtime.h>
 
 #include "fast_tile.hpp"
@@ -24,11 +21,12 @@ namespace {
 using namespace dev;
 
 // blockDim.x = T / 16 threads (128, 256 or 512) for tiles of T elements.
+// qbeg[0..8]: queue boundaries of this phase; heads[0..7]: its queue heads.
 __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restrict__ passes,
-                                                       const int2* __restrict__ items,
-                                                       const int* __restrict__ qbeg, int* ctl,
-                                                       int* counters, const float2* in,
-                                                       float2* out, float2* ws, int spin_limit) {
+                                                        const int2* __restrict__ items,
+                                                        const int* __restrict__ qbeg, int* heads,
+                                                        const float2* in, float2* out,
+                                                        float2* ws) {
   extern __shared__ float2 lds_raw[];
   __shared__ int s_item;
   const int tid = threadIdx.x;
@@ -39,7 +37,7 @@ __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restr
       int it = -1;
       while (tried < 8) {
         const int q = (q0 + tried) & 7;
-        const int k = atomicAdd(&ctl[q], 1);
+        const int k = atomicAdd(&heads[q], 1);
         if (qbeg[q] + k < qbeg[q + 1]) {
           it = qbeg[q] + k;
           break;
@@ -55,21 +53,6 @@ __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restr
     const int pi = __builtin_amdgcn_readfirstlane(I.x);
     const long long tile = __builtin_amdgcn_readfirstlane(I.y);
     const BatchPass& bp = passes[pi];
-    if (bp.need > 0) {
-      if (tid == 0) {
-        int n = 0;
-        while (__hip_atomic_load(&counters[bp.inst], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT) < bp.need) {
-          if (++n > spin_limit) {
-            atomicOr(&ctl[8], 1);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
-      }
-      __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
     const float2* src = (bp.in_buf == 0 ? in : bp.in_buf == 1 ? out : ws) + bp.in_off;
     float2* dst = (bp.out_buf == 1 ? out : ws) + bp.out_off;
     switch (bp.variant) {
@@ -89,22 +72,15 @@ __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restr
         fastk::fast_tile<16, true, false, MAP_IDENTITY, MAP_NATURAL>(bp.pd, tile, tid, src, dst, lds_raw);
         break;
     }
-    if (bp.signal) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (tid == 0)
-        __hip_atomic_fetch_add(&counters[bp.inst], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     __syncthreads();
   }
 }
 
-// Zero the queue heads and the per-lattice counters (a kernel rather than a
-// memset so that the launch can be captured into a graph).
-__global__ void __launch_bounds__(256) batch_clear_kernel(int* ctl, int* counters, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 8) ctl[i] = 0;
-  for (int k = i; k < n; k += gridDim.x * blockDim.x) counters[k] = 0;
+// Zero the queue heads (a kernel rather than a memset so that the launch can
+// be captured into a graph).
+__global__ void __launch_bounds__(64) batch_clear_kernel(int* heads, int n) {
+  const int i = threadIdx.x;
+  if (i < n) heads[i] = 0;
 }
 
 bool g_attr = false;
@@ -134,23 +110,20 @@ int batch_occupancy(int tile_lg) {
 
 const char* batch_kernel_name(int) { return "fft_batch_kernel"; }
 
-hipError_t launch_batch_clear(int* ctl, int* counters, int n, hipStream_t s) {
-  int blocks = (n + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(batch_clear_kernel, dim3(blocks), dim3(256), 0, s, ctl, counters, n);
+hipError_t launch_batch_clear(int* heads, int n, hipStream_t s) {
+  if (n < 1 || n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_clear_kernel, dim3(1), dim3(64), 0, s, heads, n);
   return hipGetLastError();
 }
 
 hipError_t launch_batch(int tile_lg, const BatchPass* passes, const int2* items, const int* qbeg,
-                        int* ctl, int* counters, const float2* in, float2* out, float2* ws,
-                        int spin_limit, int grid, hipStream_t s) {
+                        int* heads, const float2* in, float2* out, float2* ws, int grid,
+                        hipStream_t s) {
   if (tile_lg < 11 || tile_lg > 13) return hipErrorInvalidValue;
   hipError_t e = set_attr();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fft_batch_kernel, dim3(grid), dim3(1 << (tile_lg - 4)),
-                     batch_lds_bytes(1 << tile_lg), s, passes, items, qbeg, ctl, counters, in, out,
-                     ws, spin_limit);
+                     batch_lds_bytes(1 << tile_lg), s, passes, items, qbeg, heads, in, out, ws);
   return hipGetLastError();
 }
 

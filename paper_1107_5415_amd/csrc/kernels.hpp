@@ -21,13 +21,14 @@ hipError_t launch_stream_pass(const PassDesc& p, const float2* in, float2* out, 
 bool stream_supported(int L, int W, bool cols);
 const char* stream_kernel_name(const PassDesc& p);
 
-// Batched persistent launch over the BatchPass/item queues (tile_lg 11..13:
-// tiles of 2^tile_lg elements, 2^tile_lg / 16 threads per workgroup).
-// ctl: 8 queue heads, then the error flag at ctl[8]; counters: one per lattice.
+// One phase of the batched persistent launch (tile_lg 11..13: tiles of
+// 2^tile_lg elements, 2^tile_lg / 16 threads per workgroup).  qbeg[0..8]
+// bounds the eight queues of the phase in `items`; heads[0..7] must be zero
+// (launch_batch_clear) before the launch.
 hipError_t launch_batch(int tile_lg, const BatchPass* passes, const int2* items, const int* qbeg,
-                        int* ctl, int* counters, const float2* in, float2* out, float2* ws,
-                        int spin_limit, int grid, hipStream_t s);
-hipError_t launch_batch_clear(int* ctl, int* counters, int n, hipStream_t s);
+                        int* heads, const float2* in, float2* out, float2* ws, int grid,
+                        hipStream_t s);
+hipError_t launch_batch_clear(int* heads, int n, hipStream_t s);
 size_t batch_lds_bytes(int tile);
 int batch_occupancy(int tile_lg);        // resident workgroups per CU (0 on error)
 const char* batch_kernel_name(int tile_lg);

@@ -33,7 +33,7 @@ EXPORTS = [
     "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_trace_begin", "lfft_trace_end",
     "lfft_trace_get", "lfft_strerror", "lfft_batch_create", "lfft_batch_destroy",
     "lfft_batch_offsets", "lfft_batch_workspace_size", "lfft_batch_configure", "lfft_batch_config",
-    "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute", "lfft_batch_status",
+    "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute",
 ]
 
 LFFT_BATCH_LOOP = 0
@@ -98,7 +98,6 @@ def lib():
             "lfft_batch_schedule": (ctypes.c_int, [_P, ctypes.c_int, _I32P, _I64P, _I64P, _I32P]),
             "lfft_batch_tune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _FP, _P]),
             "lfft_batch_execute": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
-            "lfft_batch_status": (ctypes.c_int, [_P, _I32P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -474,11 +473,6 @@ class BatchPlan:
         _check(lib().lfft_batch_tune(self._h, _dptr(x), _dptr(out), _dptr(ws), int(reps),
                                      ctypes.byref(best), _stream_handle(x.device)), "lfft_batch_tune")
         return best.value
-
-    def status(self):
-        e = ctypes.c_int()
-        _check(lib().lfft_batch_status(self._h, ctypes.byref(e)), "lfft_batch_status")
-        return e.value
 
 
 def trace_begin(capacity=100000):

@@ -62,7 +62,6 @@ def test_batch_modes_forward_inverse(mode):
     z = plan.execute(y, inverse=True, mode=mode)
     check_all(plan, Ms, y, z, inverse=True)
     torch.cuda.synchronize()
-    assert plan.status() == 0
     assert float(torch.linalg.norm(z - x) / torch.linalg.norm(x)) < 2 * TOL
 
 
@@ -79,7 +78,6 @@ def test_batch_configurations(tile_lg, order):
     check_all(plan, Ms, x, y)
     z = plan.execute(y, inverse=True, mode=1)
     check_all(plan, Ms, y, z, inverse=True)
-    assert plan.status() == 0
 
 
 def test_batch_graph_replays():
@@ -98,7 +96,6 @@ def test_batch_graph_replays():
         x.mul_(complex(0.5, -1.25))
         x[::7] += 1.0
         torch.cuda.synchronize()
-    assert plan.status() == 0
 
 
 def test_batch_workload_tuned():
@@ -121,7 +118,6 @@ def test_batch_workload_tuned():
     assert float(torch.linalg.norm(y0 - y) / torch.linalg.norm(y0)) < 2 * TOL
     z = plan.execute(y, inverse=True, mode=2)
     assert float(torch.linalg.norm(z - x) / torch.linalg.norm(x)) < 2 * TOL
-    assert plan.status() == 0
     # the choice is remembered for the same matrices
     plan2 = lfft.BatchPlan(Ms)
     assert plan2.tune(x, reps=1) == -1.0

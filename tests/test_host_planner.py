@@ -264,6 +264,5 @@ def test_batch_schedules():
     assert lib.lfft_batch_execute(b._h, 0, 1, args[0], args[1], args[0], None) == -8
     assert lib.lfft_batch_execute(b._h, 0, 7, args[0], args[1], args[0], None) == -1
     assert lib.lfft_batch_execute(b._h, 0, 1, args[0], args[0], args[1], None) == -1
-    e = ctypes.c_int()
-    assert lib.lfft_batch_status(b._h, ctypes.byref(e)) == -8
+    assert lib.lfft_batch_tune(b._h, args[0], args[1], args[2], 1, None, None) == -8
     assert _err(lambda: lfft.BatchPlan([((1, 2), (2, 4))], host_only=True)) == -2
