@@ -135,6 +135,30 @@ def variant_batched(torch, lfft, reps):
             "graph_vs_loop": round(res["loop"]["ms"] / res["graph"]["ms"], 2)}
 
 
+def variant_split_bf16(torch, lfft, reps):
+    """Precision workload: M = [[256, 64, 0], [0, 256, 64], [0, 0, 256]]
+    (m = 2^24, eps = (64, 64, 4096)), forward FFT natural order: plain FP32
+    butterflies vs radix-16 stages as split-BF16 MFMA products."""
+    import workloads
+    cfg = workloads.CONFIGS["d3"]
+    m = 1 << 24
+    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], m)).cuda()
+    pf = lfft.LatticePlan(cfg["M"])
+    pb = lfft.LatticePlan(cfg["M"], split_bf16=True)
+    yf = torch.empty_like(x)
+    yb = torch.empty_like(x)
+    tf = _time_ms(lambda: pf.forward(x, out=yf), reps, torch)
+    tb = _time_ms(lambda: pb.forward(x, out=yb), reps, torch)
+    diff = float(torch.linalg.norm(yb - yf) / torch.linalg.norm(yf))
+    res = {}
+    for name, t in (("fp32", tf), ("split_bf16", tb)):
+        res[name] = {"ms": round(t, 4), "gflops": round(fft_flops(m) / (t / 1e3) / 1e9, 1),
+                     "alg_hbm_frac": round(16.0 * m / (t / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+    return {"workload": "d=3 M=[[256,64,0],[0,256,64],[0,0,256]] m=2^24 complex64 seed 3, "
+                        "forward FFT natural order", **res,
+            "rel_l2_bf16_vs_fp32": diff}
+
+
 def variant_grad(torch, lfft, reps):
     """Differentiation workload: M = [[1024, 256], [0, 1024]] (m = 2^20),
     batch 16, 4 quincunx levels; loss = sum_l ||d2_l||^2 + ||S(D(x)) - t||^2;
@@ -295,8 +319,9 @@ def main():
         "kernels": kernels,
     }
     if not args.no_variants:
-        log("bench: variants (batched, differentiation)")
-        out["variants"] = {"batched": variant_batched(torch, lfft, max(5, args.steps // 2)),
+        log("bench: variants (split-BF16, batched, differentiation)")
+        out["variants"] = {"split_bf16": variant_split_bf16(torch, lfft, max(5, args.steps // 2)),
+                           "batched": variant_batched(torch, lfft, max(5, args.steps // 2)),
                            "grad": variant_grad(torch, lfft, max(3, args.steps // 4))}
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host (one step)")

@@ -65,6 +65,13 @@ extern "C" {
 /* ---- plan flags --------------------------------------------------------- */
 #define LFFT_HOST_ONLY 0x1u      /* integer planning only: no device tables,
                                     execute calls return LFFT_E_STATE         */
+#define LFFT_SPLIT_BF16 0x2u     /* lfft_plan_create only: run the radix-16
+                                    stages as dense 16-point DFT-matrix
+                                    products on BF16 MFMA with split hi+lo
+                                    operands and FP32 accumulation
+                                    (accuracy bound: 1e-3 relative L2).
+                                    Needs power-of-two elementary divisors
+                                    and 32 <= m <= 2^24, else UNSUPPORTED    */
 
 /* ---- layouts (bitwise OR of one input and one output choice) ------------ */
 #define LFFT_IN_NATURAL 0x0u

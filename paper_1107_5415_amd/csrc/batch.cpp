@@ -216,7 +216,7 @@ BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags) {
     if (b->total >= (i64(1) << 40)) throw StatusError{E_UNSUPPORTED};
     b->single.assign(count, nullptr);
     b->ws_elems = (size_t)b->total;
-    if (!(flags & 1)) {
+    if (!(flags & kPlanHostOnly)) {
       const size_t n = 16 * sizeof(int);
       if (hipMalloc(&b->dheads, n) != hipSuccess) throw StatusError{E_NOMEM};
       if (hipMemset(b->dheads, 0, n) != hipSuccess) throw StatusError{E_HIP};
@@ -256,7 +256,7 @@ void configure_batch(BatchPlan* b, int tile_lg, int order) {
       b->tiled[i] = nullptr;
     }
   }
-  if (b->flags & 1) {  // host only: schedules, no device tables
+  if (b->flags & kPlanHostOnly) {  // schedules only, no device tables
     b->configured = true;
     return;
   }

@@ -68,7 +68,7 @@ extern "C" {
 int lfft_plan_create(lfft_plan_t* plan, int d, const int64_t* M, int64_t batch, uint32_t flags) {
   if (!plan) return LFFT_E_ARG;
   *plan = nullptr;
-  if (flags & ~LFFT_HOST_ONLY) return LFFT_E_ARG;
+  if (flags & ~(LFFT_HOST_ONLY | LFFT_SPLIT_BF16)) return LFFT_E_ARG;
   if (d > lfft::kMaxD) return LFFT_E_UNSUPPORTED;
   lfft::LatticePlan* p = nullptr;
   int st = guarded([&] { p = lfft::build_lattice_plan(d, M, batch, flags); });

@@ -42,7 +42,8 @@ struct StageDesc {
 };
 
 struct PassDesc {
-  int kind;                   // 0 generic kernel, 1 register-resident power-of-two kernel
+  int kind;                   // 0 generic, 1 register-resident power-of-two, 2 streaming,
+                              // 3 split-BF16 MFMA
   int P;                      // fast kernel: points per thread (16 or 32)
   int W;                      // fast kernel: pencils per workgroup
   int split;                  // fast kernel: exchange real and imaginary parts separately

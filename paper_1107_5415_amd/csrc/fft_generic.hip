@@ -171,11 +171,13 @@ __global__ void __launch_bounds__(256) pass_generic_kernel(PassDesc p, const flo
 }  // namespace
 
 const char* pass_kernel_name(const PassDesc& p) {
+  if (p.kind == 3) return mfma_kernel_name(p);
   if (p.kind == 2) return stream_kernel_name(p);
   return p.kind == 1 ? fast_kernel_name(p) : "pass_generic_kernel";
 }
 
 hipError_t launch_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
+  if (p.kind == 3) return launch_mfma_pass(p, in, out, s);
   if (p.kind == 2) return launch_stream_pass(p, in, out, s);
   if (p.kind == 1) return launch_fast_pass(p, in, out, s);
   static bool attr = false;

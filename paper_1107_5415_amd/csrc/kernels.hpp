@@ -20,6 +20,9 @@ const char* fast_kernel_name(const PassDesc& p);
 hipError_t launch_stream_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s);
 bool stream_supported(int L, int W, bool cols);
 const char* stream_kernel_name(const PassDesc& p);
+// Split-BF16 MFMA pass (descriptor kind 3): tiles of W * L = 4096 elements.
+hipError_t launch_mfma_pass(const PassDesc& p, const float2* in, float2* out, hipStream_t s);
+const char* mfma_kernel_name(const PassDesc& p);
 
 // One phase of the batched persistent launch (tile_lg 11..13: tiles of
 // 2^tile_lg elements, 2^tile_lg / 16 threads per workgroup).  qbeg[0..8]

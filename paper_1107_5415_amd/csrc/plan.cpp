@@ -337,7 +337,7 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
     for (int g = R.a; g < R.b; ++g) pow2 = pow2 && is_pow2(dg[g].n);
     if (p->tile_lg > 0) {
       // fixed tiles of 2^tile_lg elements (the schedule guarantees the shapes)
-      pd.kind = 1;
+      pd.kind = (p->flags & kPlanSplitBf16) ? 3 : 1;
       pd.P = 16;
       pd.W = (int)((i64(1) << p->tile_lg) / pd.L);
       pd.split = 0;
@@ -471,6 +471,9 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
     p->M = Mat::from(d, Mrm);
     p->batch = batch;
     p->flags = flags;
+    // the split-BF16 MFMA kernel works on fixed tiles of 4096 elements
+    if ((flags & kPlanSplitBf16) && tile_lg == 0) tile_lg = 12;
+    if ((flags & kPlanSplitBf16) && tile_lg != 12) throw StatusError{E_ARG};
     p->tile_lg = tile_lg;
     p->order = order;
     if (tile_lg != 0 && (tile_lg < 8 || tile_lg > 13)) throw StatusError{E_ARG};

@@ -23,6 +23,10 @@ enum Status : int {
   E_STATE = -8,
 };
 
+// plan flags (mirrors include/lfft.h)
+constexpr uint32_t kPlanHostOnly = 0x1;
+constexpr uint32_t kPlanSplitBf16 = 0x2;
+
 struct StatusError {
   int code;
 };

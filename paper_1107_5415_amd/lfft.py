@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblfft.so")
 
 LFFT_HOST_ONLY = 0x1
+LFFT_SPLIT_BF16 = 0x2
 LFFT_IN_NATURAL = 0x0
 LFFT_IN_GRID = 0x1
 LFFT_OUT_NATURAL = 0x0
@@ -144,14 +145,16 @@ def _dptr(t):
 class LatticePlan:
     """Plan of the lattice FFT on P(M) for `batch` signals (lfft_plan_*)."""
 
-    def __init__(self, M, batch=1, host_only=False):
+    def __init__(self, M, batch=1, host_only=False, split_bf16=False):
         self.M = _mat(M)
         self.d = self.M.shape[0]
         self.batch = int(batch)
         self.host_only = bool(host_only)
+        self.split_bf16 = bool(split_bf16)
+        flags = (LFFT_HOST_ONLY if host_only else 0) | (LFFT_SPLIT_BF16 if split_bf16 else 0)
         h = _P()
-        _check(lib().lfft_plan_create(ctypes.byref(h), self.d, _ptr64(self.M), self.batch,
-                                      LFFT_HOST_ONLY if host_only else 0), "lfft_plan_create")
+        _check(lib().lfft_plan_create(ctypes.byref(h), self.d, _ptr64(self.M), self.batch, flags),
+               "lfft_plan_create")
         self._h = h
         self._ws = None
         q = self.query()

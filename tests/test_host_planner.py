@@ -266,3 +266,16 @@ def test_batch_schedules():
     assert lib.lfft_batch_execute(b._h, 0, 1, args[0], args[0], args[1], None) == -1
     assert lib.lfft_batch_tune(b._h, args[0], args[1], args[2], 1, None, None) == -8
     assert _err(lambda: lfft.BatchPlan([((1, 2), (2, 4))], host_only=True)) == -2
+
+
+def test_split_bf16_plans():
+    """The split-BF16 flag plans fixed 4096-element tiles: power-of-two
+    elementary divisors and 32 <= m <= 2^24 only."""
+    p = lfft.LatticePlan(((256, 64, 0), (0, 256, 64), (0, 0, 256)), host_only=True, split_bf16=True)
+    assert p.query()["passes"] == 2
+    p = lfft.LatticePlan(((32, 8), (0, 32)), host_only=True, split_bf16=True)
+    assert p.query()["passes"] == 1
+    assert _err(lambda: lfft.LatticePlan(((32, 8), (-8, 32)), host_only=True, split_bf16=True)) == -5
+    assert _err(lambda: lfft.LatticePlan(((1 << 13, 0), (0, 1 << 12)), host_only=True,
+                                         split_bf16=True)) == -5
+    assert _err(lambda: lfft.LatticePlan(((4, 0), (0, 4)), host_only=True, split_bf16=True)) == -5
