@@ -93,8 +93,8 @@ void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
       if (bp.pd.kind != 1 || bp.pd.P != 16 || bp.pd.split ||
           (i64)bp.pd.W * bp.pd.L != (i64(1) << b->tile_lg))
         throw StatusError{E_STATE};
-      bp.in_off = b->off[i];
-      bp.out_off = b->off[i];
+      bp.in_off = first ? b->in_off[i] : b->ws_off[i];
+      bp.out_off = last ? b->out_off[i] : b->ws_off[i];
       bp.in_buf = first ? 0 : 2;
       bp.out_buf = last ? 1 : 2;
       bp.variant = variant_of(bp.pd, first, last);
@@ -168,10 +168,13 @@ void enqueue_persistent(BatchPlan* b, bool inverse, const void* in, void* out, v
         if (p && (int)p->fwd.passes.size() > ph) bytes += 16.0 * (double)b->m[i];
       }
       TraceScope ts(trace && trace_on() ? batch_kernel_name(b->tile_lg) : nullptr, bytes, s);
+      // never more workgroups than items: idle ones would only contend for
+      // the queue heads
+      const int grid = std::min(b->grid, std::max(8, D.phase_items[ph]));
       e = launch_batch(b->tile_lg, static_cast<const BatchPass*>(D.dpass),
-                       static_cast<const int2*>(D.ditems), D.qbeg + 8 * ph, b->dheads + 8 * ph,
-                       static_cast<const float2*>(in), static_cast<float2*>(out),
-                       static_cast<float2*>(ws), b->grid, s);
+                       static_cast<const int2*>(D.ditems), D.qbeg + 8 * ph,
+                       b->dheads + 8 * kHeadStride * ph, static_cast<const float2*>(in),
+                       static_cast<float2*>(out), static_cast<float2*>(ws), grid, s);
       if (e != hipSuccess) throw StatusError{E_HIP};
     }
   }
@@ -179,8 +182,9 @@ void enqueue_persistent(BatchPlan* b, bool inverse, const void* in, void* out, v
   for (int i = 0; i < b->count; ++i) {
     if (b->tiled[i]) continue;
     LatticePlan* p = single_plan(b, i);
-    exec_lattice(p, inverse, false, false, static_cast<const float2*>(in) + b->off[i],
-                 static_cast<float2*>(out) + b->off[i], ws, p->m, p->m, s);
+    exec_lattice(p, inverse, false, false, static_cast<const float2*>(in) + b->in_off[i],
+                 static_cast<float2*>(out) + b->out_off[i], static_cast<float2*>(ws) + b->ws_off[i],
+                 p->m, p->m, s);
   }
 }
 
@@ -195,6 +199,12 @@ std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 }  // namespace
 
 BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags) {
+  return build_batch_plan_at(count, d, Ms, nullptr, nullptr, nullptr, 0, flags, 12, 0);
+}
+
+BatchPlan* build_batch_plan_at(int count, int d, const i64* Ms, const i64* in_off,
+                               const i64* out_off, const i64* ws_off, size_t ws_elems,
+                               uint32_t flags, int tile_lg, int order) {
   if (count < 1 || d < 1 || d > kMaxD || !Ms) throw StatusError{E_ARG};
   auto* b = new BatchPlan();
   try {
@@ -215,15 +225,25 @@ BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags) {
     b->total = b->off.back();
     if (b->total >= (i64(1) << 40)) throw StatusError{E_UNSUPPORTED};
     b->single.assign(count, nullptr);
-    b->ws_elems = (size_t)b->total;
+    if (in_off && out_off && ws_off) {
+      b->in_off.assign(in_off, in_off + count);
+      b->out_off.assign(out_off, out_off + count);
+      b->ws_off.assign(ws_off, ws_off + count);
+      b->ws_elems = ws_elems;
+    } else {
+      b->in_off.assign(b->off.begin(), b->off.end() - 1);
+      b->out_off = b->in_off;
+      b->ws_off = b->in_off;
+      b->ws_elems = (size_t)b->total;
+    }
     if (!(flags & kPlanHostOnly)) {
-      const size_t n = 16 * sizeof(int);
+      const size_t n = 16 * kHeadStride * sizeof(int);
       if (hipMalloc(&b->dheads, n) != hipSuccess) throw StatusError{E_NOMEM};
       if (hipMemset(b->dheads, 0, n) != hipSuccess) throw StatusError{E_HIP};
       if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
         throw StatusError{E_HIP};
     }
-    configure_batch(b, 12, 0);
+    configure_batch(b, tile_lg, order);
   } catch (...) {
     free_batch_plan(b);
     throw;
@@ -280,8 +300,9 @@ void exec_batch(BatchPlan* b, bool inverse, int mode, const void* in, void* out,
   if (mode == BATCH_LOOP) {
     for (int i = 0; i < b->count; ++i) {
       LatticePlan* p = single_plan(b, i);
-      exec_lattice(p, inverse, false, false, static_cast<const float2*>(in) + b->off[i],
-                   static_cast<float2*>(out) + b->off[i], ws, p->m, p->m, s);
+      exec_lattice(p, inverse, false, false, static_cast<const float2*>(in) + b->in_off[i],
+                   static_cast<float2*>(out) + b->out_off[i],
+                   static_cast<float2*>(ws) + b->ws_off[i], p->m, p->m, s);
     }
     return;
   }

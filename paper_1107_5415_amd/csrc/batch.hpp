@@ -28,6 +28,9 @@ struct BatchPlan {
   int count = 0, d = 0;
   std::vector<i64> Ms;                  // count * d * d, row-major per lattice
   std::vector<i64> m, off;              // off: count + 1 prefix offsets
+  // element offsets of every lattice's signal in the input, output and
+  // workspace buffers (the public plan uses off[i] for all three)
+  std::vector<i64> in_off, out_off, ws_off;
   i64 total = 0;
   uint32_t flags = 0;
   int tile_lg = 12, order = 0;
@@ -36,7 +39,7 @@ struct BatchPlan {
   std::vector<LatticePlan*> single;     // default plans, built on first per-lattice use
   int eligible = 0;
   BatchDir dir[2];                      // forward, inverse
-  int* dheads = nullptr;                // 16 queue heads (8 per phase)
+  int* dheads = nullptr;                // 16 queue heads (8 per phase), kHeadStride apart
   int grid = 0;
   hipStream_t cap = nullptr;            // private stream for graph capture
   std::map<std::tuple<int, const void*, void*, void*>, hipGraphExec_t> graphs;
@@ -44,6 +47,11 @@ struct BatchPlan {
 };
 
 BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags);
+// Same with explicit per-lattice offsets (in, out and workspace elements; the
+// workspace slot of lattice i holds m_i elements); ws_elems = workspace size.
+BatchPlan* build_batch_plan_at(int count, int d, const i64* Ms, const i64* in_off,
+                               const i64* out_off, const i64* ws_off, size_t ws_elems,
+                               uint32_t flags, int tile_lg, int order);
 void free_batch_plan(BatchPlan* b);
 // (Re)build the fixed-tile schedules and device queues for one configuration.
 void configure_batch(BatchPlan* b, int tile_lg, int order);

@@ -46,48 +46,66 @@ __device__ __forceinline__ BfGeom geom(const StageDesc& st, int bl) {
   return g;
 }
 
+// One side of a pencil: the signal's base pointer and 32-bit element
+// offsets inside the signal (the planner keeps these lattices below 2^30
+// points).
 template <int MODE>
 struct Addr {
-  // per-thread base for one side
-  long long lin_base;   // IDENTITY: b*bstride + (o*L*S + s); LINEAR: b*bstride + To[o] + Ts[s]
+  const float2* base;
+  int lin;              // IDENTITY: o*L*S + s; LINEAR: To[o] + Ts[s]
   int cbase[4];         // NATURAL: To[o] (+) Ts[s]
 };
 
 template <int MODE>
-__device__ __forceinline__ void addr_init(Addr<MODE>& A, const MapDesc& m, const Pencil& pc,
-                                          int L, int S) {
+__device__ __forceinline__ void addr_init(Addr<MODE>& A, const MapDesc& m, const float2* buf,
+                                          const Pencil& pc, int L, int S) {
+  A.base = buf + pc.b * m.bstride;
   if constexpr (MODE == MAP_IDENTITY) {
-    A.lin_base = pc.b * m.bstride + (long long)pc.o * L * S + pc.s;
+    A.lin = pc.o * L * S + pc.s;
   } else if constexpr (MODE == MAP_LINEAR) {
-    A.lin_base = pc.b * m.bstride + (long long)m.To[pc.o].x + (long long)m.Ts[pc.s].x;
+    A.lin = m.To[pc.o].x + m.Ts[pc.s].x;
   } else {
     A.cbase[0] = A.cbase[1] = A.cbase[2] = A.cbase[3] = 0;
-    gadd32(m, A.cbase, m.To[pc.o]);
-    gadd32(m, A.cbase, m.Ts[pc.s]);
-    A.lin_base = pc.b * m.bstride;
+    if (m.d == 2) {
+      gadd2(m, A.cbase[0], A.cbase[1], m.To[pc.o]);
+      gadd2(m, A.cbase[0], A.cbase[1], m.Ts[pc.s]);
+    } else {
+      gadd32(m, A.cbase, m.To[pc.o]);
+      gadd32(m, A.cbase, m.Ts[pc.s]);
+    }
   }
 }
 
-// Visit the global indices of positions l0 + i*step, i < R.
+// Visit the element offsets of positions l0 + i*step, i < R.
 template <int MODE, int R, class F>
 __device__ __forceinline__ void for_positions(const Addr<MODE>& A, const MapDesc& m, int S, int l0,
                                               int step, F&& f) {
   if constexpr (MODE == MAP_IDENTITY) {
-    long long a = A.lin_base + (long long)l0 * S;
-    const long long st = (long long)step * S;
+    const int a = A.lin + l0 * S;
 #pragma unroll
-    for (int i = 0; i < R; ++i) f(i, a + i * st);
+    for (int i = 0; i < R; ++i) f(i, a + i * step * S);
   } else if constexpr (MODE == MAP_LINEAR) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) f(i, A.lin_base + (long long)m.Tl[l0 + i * step].x);
+    for (int i = 0; i < R; ++i) f(i, A.lin + m.Tl[l0 + i * step].x);
   } else {
-    int c[4] = {A.cbase[0], A.cbase[1], A.cbase[2], A.cbase[3]};
-    gadd32(m, c, m.Tl[l0]);
     const int4 D = m.Tl[step];
+    if (m.d == 2) {
+      int c0 = A.cbase[0], c1 = A.cbase[1];
+      gadd2(m, c0, c1, m.Tl[l0]);
+      const int h11 = m.H[1][1];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      f(i, A.lin_base + nat_index32(m, c));
-      if (i + 1 < R) gadd32(m, c, D);
+      for (int i = 0; i < R; ++i) {
+        f(i, c0 * h11 + c1);
+        if (i + 1 < R) gadd2(m, c0, c1, D);
+      }
+    } else {
+      int c[4] = {A.cbase[0], A.cbase[1], A.cbase[2], A.cbase[3]};
+      gadd32(m, c, m.Tl[l0]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        f(i, nat_index_i(m, c));
+        if (i + 1 < R) gadd32(m, c, D);
+      }
     }
   }
 }
@@ -99,15 +117,14 @@ __device__ __forceinline__ void dftR(float2* v, int sign) {
 
 template <int P, int R, int MIN>
 __device__ __forceinline__ void load_first(float2* v, const PassDesc& p, const Addr<MIN>& A,
-                                           const float2* __restrict__ in, int jt, int TPP,
-                                           bool active) {
+                                           int jt, int TPP, bool active) {
   const StageDesc& st = p.st[0];
 #pragma unroll
   for (int q = 0; q < P / R; ++q) {
     BfGeom g = geom(st, jt + TPP * q);
     if (active) {
       for_positions<MIN, R>(A, p.in, p.S, g.in0, g.in_step,
-                            [&](int i, long long idx) { v[q * R + i] = in[idx]; });
+                            [&](int i, int off) { v[q * R + i] = A.base[(unsigned)off]; });
     } else {
 #pragma unroll
       for (int i = 0; i < R; ++i) v[q * R + i] = make_float2(0.f, 0.f);
@@ -227,13 +244,15 @@ __device__ __forceinline__ void lds_read(float2* v, const void* lds, const Stage
 
 template <int P, int R, int MOUT>
 __device__ __forceinline__ void store_last_r(const float2* v, const PassDesc& p,
-                                             const Addr<MOUT>& A, float2* __restrict__ out,
-                                             int jt, int TPP, const Pencil& pc) {
+                                             const Addr<MOUT>& A, int jt, int TPP,
+                                             const Pencil& pc) {
   const StageDesc& st = p.st[p.nst - 1];
+  float2* out = const_cast<float2*>(A.base);
+  const bool scaled = p.scale != 1.0f;
 #pragma unroll
   for (int q = 0; q < P / R; ++q) {
     BfGeom g = geom(st, jt + TPP * q);
-    for_positions<MOUT, R>(A, p.out, p.S, g.out0, g.out_step, [&](int i, long long idx) {
+    for_positions<MOUT, R>(A, p.out, p.S, g.out0, g.out_step, [&](int i, int off) {
       float2 x = v[q * R + i];
       if (p.post) {
         const int l = (g.out0 + i * g.out_step) % p.post_lmod;
@@ -243,18 +262,19 @@ __device__ __forceinline__ void store_last_r(const float2* v, const PassDesc& p,
         if (p.sign > 0) w.y = -w.y;
         x = c_mul(x, w);
       }
-      x.x *= p.scale;
-      x.y *= p.scale;
-      out[idx] = x;
+      if (scaled) {
+        x.x *= p.scale;
+        x.y *= p.scale;
+      }
+      out[(unsigned)off] = x;
     });
   }
 }
 
 template <int P, int MOUT>
 __device__ __forceinline__ void store_last(const float2* v, const PassDesc& p, const Addr<MOUT>& A,
-                                           float2* __restrict__ out, int jt, int TPP,
-                                           const Pencil& pc) {
-  LFFT_RADIX_SWITCH(p.st[p.nst - 1].radix, (store_last_r<P, RR, MOUT>(v, p, A, out, jt, TPP, pc)));
+                                           int jt, int TPP, const Pencil& pc) {
+  LFFT_RADIX_SWITCH(p.st[p.nst - 1].radix, (store_last_r<P, RR, MOUT>(v, p, A, jt, TPP, pc)));
 }
 
 // Process tile `tile` of pass p with NT = W * L / P threads (tid < NT);
@@ -287,8 +307,8 @@ __device__ __forceinline__ void fast_tile(const PassDesc& p, long long tile, int
   float2 v[P];
   {
     Addr<MIN> A;
-    addr_init<MIN>(A, p.in, pc, L, S);
-    LFFT_RADIX_SWITCH(p.st[0].radix, (load_first<P, RR, MIN>(v, p, A, in, jt, TPP, pc.active)));
+    addr_init<MIN>(A, p.in, in, pc, L, S);
+    LFFT_RADIX_SWITCH(p.st[0].radix, (load_first<P, RR, MIN>(v, p, A, jt, TPP, pc.active)));
   }
   float2 twb[8];
   LFFT_RADIX_SWITCH(p.st[0].radix, (prefetch_tw<P, RR>(twb, p.st[0], jt, TPP)));
@@ -317,8 +337,8 @@ __device__ __forceinline__ void fast_tile(const PassDesc& p, long long tile, int
   }
   if (pc.active) {
     Addr<MOUT> A;
-    addr_init<MOUT>(A, p.out, pc, L, S);
-    store_last<P, MOUT>(v, p, A, out, jt, TPP, pc);
+    addr_init<MOUT>(A, p.out, out, pc, L, S);
+    store_last<P, MOUT>(v, p, A, jt, TPP, pc);
   }
 }
 

@@ -21,7 +21,9 @@ namespace {
 using namespace dev;
 
 // blockDim.x = T / 16 threads (128, 256 or 512) for tiles of T elements.
-// qbeg[0..8]: queue boundaries of this phase; heads[0..7]: its queue heads.
+// qbeg[0..8]: queue boundaries of this phase; heads[32 q]: head of queue q
+// (one 128-byte line per head, so claims on different queues do not
+// serialise on one line).
 __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restrict__ passes,
                                                         const int2* __restrict__ items,
                                                         const int* __restrict__ qbeg, int* heads,
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restr
       int it = -1;
       while (tried < 8) {
         const int q = (q0 + tried) & 7;
-        const int k = atomicAdd(&heads[q], 1);
+        const int k = atomicAdd(&heads[kHeadStride * q], 1);
         if (qbeg[q] + k < qbeg[q + 1]) {
           it = qbeg[q] + k;
           break;
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(512) fft_batch_kernel(const BatchPass* __restr
 // be captured into a graph).
 __global__ void __launch_bounds__(64) batch_clear_kernel(int* heads, int n) {
   const int i = threadIdx.x;
-  if (i < n) heads[i] = 0;
+  if (i < n) heads[kHeadStride * i] = 0;
 }
 
 bool g_attr = false;

@@ -78,6 +78,35 @@ __device__ __forceinline__ float2 root32(int k, int sign) {
   return make_float2(C[k], sign < 0 ? -Sn[k] : Sn[k]);
 }
 
+// o * exp(sign 2 pi i K / R) for a compile-time K < R / 2: the factors 1
+// and sign * i cost no multiplication (IEEE semantics keep the compiler
+// from dropping products with the constant 0 by itself).
+template <int R, int K>
+__device__ __forceinline__ float2 rot_k(float2 o, int sign) {
+  if constexpr (K == 0) {
+    return o;
+  } else if constexpr (4 * K == R) {
+    return c_muli(o, sign);
+  } else if constexpr (R == 32) {
+    return c_mul(root32(K, sign), o);
+  } else {
+    return c_mul(root16(K * (16 / R), sign), o);
+  }
+}
+
+// butterflies k = K .. R/2 - 1 of the last combining step
+template <int R, int K>
+struct Combine {
+  __device__ __forceinline__ static void run(float2* v, const float2* e, const float2* o, int sign) {
+    if constexpr (K < R / 2) {
+      const float2 t = rot_k<R, K>(o[K], sign);
+      v[K] = c_add(e[K], t);
+      v[K + R / 2] = c_sub(e[K], t);
+      Combine<R, K + 1>::run(v, e, o, sign);
+    }
+  }
+};
+
 template <int R>
 __device__ __forceinline__ void dft_pow2(float2* v, int sign) {
   static_assert(R <= 32, "radix above 32");
@@ -90,12 +119,7 @@ __device__ __forceinline__ void dft_pow2(float2* v, int sign) {
   }
   dft_pow2<R / 2>(e, sign);
   dft_pow2<R / 2>(o, sign);
-#pragma unroll
-  for (int k = 0; k < R / 2; ++k) {
-    float2 t = (R == 32) ? c_mul(root32(k, sign), o[k]) : c_mul(root16(k * (16 / R), sign), o[k]);
-    v[k] = c_add(e[k], t);
-    v[k + R / 2] = c_sub(e[k], t);
-  }
+  Combine<R, 0>::run(v, e, o, sign);
 }
 
 __device__ __forceinline__ void dft3(float2* v, int sign) {
@@ -193,6 +217,29 @@ __device__ __forceinline__ long long xcd_tile(long long i, long long n) {
   const long long per = n >> 3, rem = n & 7;
   const long long x = i & 7, k = i >> 3;
   return x * per + (x < rem ? x : rem) + k;
+}
+
+// Natural box of a 2-D lattice, column Hermite form [[h00, h01], [0, h11]]:
+// c += b for reduced c and b.  c1 + b1 < 2 h11 needs at most one column-1
+// subtraction; c0 then lies in (-h00, 2 h00 - 1) and needs at most one
+// correction by h00.
+__device__ __forceinline__ void gadd2(const MapDesc& m, int& c0, int& c1, int4 b) {
+  c0 += b.x;
+  c1 += b.y;
+  const bool o1 = c1 >= m.H[1][1];
+  c1 -= o1 ? m.H[1][1] : 0;
+  c0 -= o1 ? m.H[0][1] : 0;
+  c0 += c0 < 0 ? m.H[0][0] : 0;
+  c0 -= c0 >= m.H[0][0] ? m.H[0][0] : 0;
+}
+
+// linear natural index (int: the planner keeps these lattices below 2^30 points)
+__device__ __forceinline__ int nat_index_i(const MapDesc& m, const int* c) {
+  int idx = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i < m.d) idx += c[i] * (int)m.box_stride[i];
+  return idx;
 }
 
 __device__ __forceinline__ long long nat_index32(const MapDesc& m, const int* c) {

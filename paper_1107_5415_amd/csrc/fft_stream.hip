@@ -1,14 +1,15 @@
-// Persistent, register double-buffered FFT pass for single-digit power-of-two
-// pencils (the dominant case: the last axis of the eps-grid in rows, or one
-// outer axis in column tiles).
+// Persistent FFT pass for single-digit power-of-two pencils (the dominant
+// case: the last axis of the eps-grid in rows, or one outer axis in column
+// tiles).
 //
 // Every workgroup stays resident and walks a contiguous range of tiles of
-// its XCD.  While tile t is transformed (radix-16/8/4/2 Stockham stages in
-// VGPRs, padded LDS transposes between stages), the global loads of tile
-// t + 1 are already in flight in a second register set, so the HBM stream
-// never waits for the arithmetic.  Pencil length L, pencils per tile W and
-// the radix sequence are compile-time constants, so all butterfly geometry
-// folds to constants and shifts.
+// its XCD; two workgroups per CU overlap one tile's HBM traffic with the
+// other's arithmetic.  A tile is transformed by radix-32/16/8 Stockham
+// stages in VGPRs with padded LDS transposes between stages.  Pencil length
+// L, pencils per tile W and the radix sequence are compile-time constants,
+// so the butterfly geometry and the LDS offsets fold to constants; the
+// tile's signal and pencil indices are uniform (scalar unit) and every
+// global access is a 32-bit offset from a uniform base.
 #include <hip/hip_runtime.h>
 
 #include "fft_common.hpp"
@@ -20,7 +21,6 @@ namespace {
 using namespace dev;
 
 constexpr int kP = 32;  // values per thread
-constexpr bool kDoubleBufferRows = false;
 // workgroups per CU the register budget is sized for
 constexpr int kRowsWgPerCu = 2;
 constexpr int kColsWgPerCu = 1;
@@ -62,88 +62,103 @@ struct Lg {
   static constexpr int value = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
 };
 
+// One side (input or output) of a tile: the signal's base pointer is uniform
+// over the workgroup (a tile never straddles two signals), every per-lane
+// offset is a 32-bit element index inside the signal.
 template <int MODE>
 struct Side {
-  long long lin;   // IDENTITY / LINEAR base, or batch offset for NATURAL
-  int c[4];        // NATURAL: To[o] (+) Ts[s]
+  const float2* base;
+  int lin;     // IDENTITY / LINEAR: offset of position 0 of the lane's pencil
+  int c[4];    // NATURAL: To[o] (+) Ts[s]
 };
 
 template <int MODE>
-__device__ __forceinline__ void side_init(Side<MODE>& A, const MapDesc& m, long long b, int o, int s,
-                                          int L, int S) {
+__device__ __forceinline__ void side_init(Side<MODE>& A, const MapDesc& m, const float2* buf,
+                                          long long b, int o, int s, int L, int S) {
+  A.base = buf + b * m.bstride;
   if constexpr (MODE == MAP_IDENTITY) {
-    A.lin = b * m.bstride + (long long)o * L * S + s;
+    A.lin = o * L * S + s;
   } else if constexpr (MODE == MAP_LINEAR) {
-    A.lin = b * m.bstride + (long long)m.To[o].x + (long long)m.Ts[s].x;
+    A.lin = m.To[o].x + m.Ts[s].x;
   } else {
     A.c[0] = A.c[1] = A.c[2] = A.c[3] = 0;
-    gadd32(m, A.c, m.To[o]);
-    gadd32(m, A.c, m.Ts[s]);
-    A.lin = b * m.bstride;
-  }
-}
-
-// global index of positions l0 + i*step (i < R) on one side
-template <int MODE, int R, class F>
-__device__ __forceinline__ void side_positions(const Side<MODE>& A, const MapDesc& m, int S, int l0,
-                                               int step, F&& f) {
-  if constexpr (MODE == MAP_IDENTITY) {
-    const long long a = A.lin + (long long)l0 * S;
-#pragma unroll
-    for (int i = 0; i < R; ++i) f(i, a + (long long)(i * step) * S);
-  } else if constexpr (MODE == MAP_LINEAR) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) f(i, A.lin + (long long)m.Tl[l0 + i * step].x);
-  } else {
-    int c[4] = {A.c[0], A.c[1], A.c[2], A.c[3]};
-    gadd32(m, c, m.Tl[l0]);
-    const int4 D = m.Tl[step];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      f(i, A.lin + nat_index32(m, c));
-      if (i + 1 < R) gadd32(m, c, D);
+    if (m.d == 2) {
+      gadd2(m, A.c[0], A.c[1], m.To[o]);
+      gadd2(m, A.c[0], A.c[1], m.Ts[s]);
+    } else {
+      gadd32(m, A.c, m.To[o]);
+      gadd32(m, A.c, m.Ts[s]);
     }
   }
 }
 
+// element offsets of positions l0 + i*step (i < R) on one side
+template <int MODE, int R, class F>
+__device__ __forceinline__ void side_positions(const Side<MODE>& A, const MapDesc& m, int S, int l0,
+                                               int step, F&& f) {
+  if constexpr (MODE == MAP_IDENTITY) {
+    const int a = A.lin + l0 * S;
+#pragma unroll
+    for (int i = 0; i < R; ++i) f(i, a + i * step * S);
+  } else if constexpr (MODE == MAP_LINEAR) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) f(i, A.lin + m.Tl[l0 + i * step].x);
+  } else {
+    const int4 D = m.Tl[step];
+    if (m.d == 2) {
+      // two-dimensional box: two coordinates, index c0 * h11 + c1
+      int c0 = A.c[0], c1 = A.c[1];
+      gadd2(m, c0, c1, m.Tl[l0]);
+      const int h11 = m.H[1][1];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        f(i, c0 * h11 + c1);
+        if (i + 1 < R) gadd2(m, c0, c1, D);
+      }
+    } else {
+      int c[4] = {A.c[0], A.c[1], A.c[2], A.c[3]};
+      gadd32(m, c, m.Tl[l0]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        f(i, nat_index_i(m, c));
+        if (i + 1 < R) gadd32(m, c, D);
+      }
+    }
+  }
+}
+
+// Uniform decomposition of a tile: its W pencils belong to one signal b;
+// rows: pencil o = o0 + w (s = 0), column tiles: o = o0, s = s0 + w.
 struct TileId {
   long long b;
-  int o, s;
-  bool active;
+  int o0, s0;
 };
 
-template <bool COLS>
-__device__ __forceinline__ TileId tile_pencil(long long tile, int w, int W, long long npen, int O,
-                                              int S) {
+template <int W>
+__device__ __forceinline__ TileId tile_of(long long tile, int O, int S) {
+  const long long pen0 = tile * W;
+  const long long per = (long long)O * S;
   TileId t;
-  const long long pen = tile * W + w;
-  t.active = pen < npen;
-  const long long pp = t.active ? pen : 0;
-  const long long bo = pp / S;
-  t.s = (int)(pp - bo * S);
-  t.b = bo / O;
-  t.o = (int)(bo - t.b * O);
+  t.b = pen0 / per;
+  const long long r = pen0 - t.b * per;
+  t.o0 = (int)(r / S);
+  t.s0 = (int)(r - (long long)t.o0 * S);
   return t;
 }
 
 // loads of the first stage's inputs of one tile into v
-template <int L, int MIN>
+template <int L, bool COLS, int MIN>
 __device__ __forceinline__ void load_tile(float2* v, const PassDesc& p, const float2* __restrict__ in,
-                                          const TileId& t, int jt) {
+                                          const TileId& t, int w, int jt) {
   constexpr int R = StageR<L, 0>::value;
   constexpr int TPP = L / kP;
-  if (!t.active) {
-#pragma unroll
-    for (int i = 0; i < kP; ++i) v[i] = make_float2(0.f, 0.f);
-    return;
-  }
   Side<MIN> A;
-  side_init<MIN>(A, p.in, t.b, t.o, t.s, L, p.S);
+  side_init<MIN>(A, p.in, in, t.b, COLS ? t.o0 : t.o0 + w, COLS ? t.s0 + w : t.s0, L, p.S);
 #pragma unroll
   for (int q = 0; q < kP / R; ++q) {
     const int j = jt + TPP * q;
     side_positions<MIN, R>(A, p.in, p.S, j, L / R,
-                           [&](int i, long long idx) { v[q * R + i] = in[idx]; });
+                           [&](int i, int off) { v[q * R + i] = A.base[(unsigned)off]; });
   }
 }
 
@@ -209,19 +224,32 @@ __device__ __forceinline__ int slds(int l, int w) {
   return sphys(COLS ? l * W + w : w * L + l);
 }
 
+// LDS word of pencil position l0 + delta where delta * (COLS ? W : 1) is a
+// multiple of 16 or, for rows, l0 is a multiple of 16 and delta < 16: then
+// sphys is linear in delta and the offset folds into the instruction.
+template <bool COLS, int L, int W>
+__device__ __forceinline__ int slds_off(int base_e, int delta) {
+  const int d = COLS ? delta * W : delta;
+  return base_e + d + (d >> 4);
+}
+
 // write stage SI outputs, read stage SI+1 inputs (one part: 0 both, 1 re, 2 im)
 template <int L, int W, bool COLS, int SI, int PART>
 __device__ __forceinline__ void exch_write(const float2* v, void* lds, int jt, int w) {
   constexpr int R = StageR<L, SI>::value;
   constexpr int Ns = StageNs<L, SI>::value;
   constexpr int TPP = L / kP;
+  // linear offsets: rows need Ns % 16 == 0 or (Ns == 1 and R % 16 == 0);
+  // column tiles need (Ns * W) % 16 == 0
+  constexpr bool lin = COLS ? ((Ns * W) % 16 == 0) : (Ns % 16 == 0 || (Ns == 1 && R % 16 == 0));
 #pragma unroll
   for (int q = 0; q < kP / R; ++q) {
     const int j = jt + TPP * q;
     const int out0 = (j / Ns) * Ns * R + (j & (Ns - 1));
+    const int eb = slds<COLS, L, W>(out0, w);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const int e = slds<COLS, L, W>(out0 + i * Ns, w);
+      const int e = lin ? slds_off<COLS, L, W>(eb, i * Ns) : slds<COLS, L, W>(out0 + i * Ns, w);
       if constexpr (PART == 0)
         static_cast<float2*>(lds)[e] = v[q * R + i];
       else if constexpr (PART == 1)
@@ -236,12 +264,14 @@ template <int L, int W, bool COLS, int SI, int PART>
 __device__ __forceinline__ void exch_read(float2* v, const void* lds, int jt, int w) {
   constexpr int R = StageR<L, SI>::value;
   constexpr int TPP = L / kP;
+  static_assert((L / R) % 16 == 0, "read stride must keep LDS offsets linear");
 #pragma unroll
   for (int q = 0; q < kP / R; ++q) {
     const int j = jt + TPP * q;
+    const int eb = slds<COLS, L, W>(j, w);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const int e = slds<COLS, L, W>(j + i * (L / R), w);
+      const int e = slds_off<COLS, L, W>(eb, i * (L / R));
       if constexpr (PART == 0)
         v[q * R + i] = static_cast<const float2*>(lds)[e];
       else if constexpr (PART == 1)
@@ -278,37 +308,46 @@ __device__ __forceinline__ void stages_from(float2* v, float2* twb, void* lds, c
   }
 }
 
-template <int L, int MOUT>
+template <int L, bool COLS, int MOUT>
 __device__ __forceinline__ void store_tile(const float2* v, const PassDesc& p,
-                                           float2* __restrict__ out, const TileId& t, int jt) {
+                                           float2* __restrict__ out, const TileId& t, int w,
+                                           int jt) {
   constexpr int NS = NStages<L>::value;
   constexpr int R = StageR<L, NS - 1>::value;
   constexpr int Ns = StageNs<L, NS - 1>::value;
   constexpr int TPP = L / kP;
-  if (!t.active) return;
+  const int o = COLS ? t.o0 : t.o0 + w;
+  const int s = COLS ? t.s0 + w : t.s0;
   Side<MOUT> A;
-  side_init<MOUT>(A, p.out, t.b, t.o, t.s, L, p.S);
+  side_init<MOUT>(A, p.out, out, t.b, o, s, L, p.S);
+  float2* base = const_cast<float2*>(A.base);
+  const bool scaled = p.scale != 1.0f;
 #pragma unroll
   for (int q = 0; q < kP / R; ++q) {
     const int j = jt + TPP * q;
     const int out0 = (j / Ns) * Ns * R + (j & (Ns - 1));
-    side_positions<MOUT, R>(A, p.out, p.S, out0, Ns, [&](int i, long long idx) {
+    side_positions<MOUT, R>(A, p.out, p.S, out0, Ns, [&](int i, int off) {
       float2 x = v[q * R + i];
       if (p.post) {
         const int l = (out0 + i * Ns) % p.post_lmod;
-        const long long lo = (t.s / p.lo_div) % p.lo_n;
+        const long long lo = (s / p.lo_div) % p.lo_n;
         const long long tt = ((long long)l * lo) % p.postN;
         float2 wv = c_mul(p.tw_hi[tt >> 12], p.tw_lo[tt & 4095]);
         if (p.sign > 0) wv.y = -wv.y;
         x = c_mul(x, wv);
       }
-      x.x *= p.scale;
-      x.y *= p.scale;
-      out[idx] = x;
+      if (scaled) {
+        x.x *= p.scale;
+        x.y *= p.scale;
+      }
+      base[(unsigned)off] = x;
     });
   }
 }
 
+// Every launch satisfies (checked on the host): W divides the pencils of one
+// signal (O * S), so all tiles are full and never straddle two signals, and
+// one signal has fewer than 2^28 points (32-bit element offsets).
 template <int L, int W, bool COLS, bool SPLIT, int MIN, int MOUT>
 __global__ void __launch_bounds__(W * L / kP, (COLS ? kColsWgPerCu : kRowsWgPerCu)) fft_stream_kernel(PassDesc p, const float2* __restrict__ in,
                                                                 float2* __restrict__ out) {
@@ -319,7 +358,7 @@ __global__ void __launch_bounds__(W * L / kP, (COLS ? kColsWgPerCu : kRowsWgPerC
   const int w = COLS ? tid % W : tid / TPP;
   const int jt = COLS ? tid / W : tid % TPP;
   const long long npen = p.batch * (long long)p.O * p.S;
-  const long long ntiles = (npen + W - 1) / W;
+  const long long ntiles = npen / W;
   // persistent schedule: XCD x owns tiles [beg_x, end_x); its k-th workgroup
   // takes beg_x + k, beg_x + k + nwg_x, ...
   const long long G = gridDim.x;
@@ -332,37 +371,12 @@ __global__ void __launch_bounds__(W * L / kP, (COLS ? kColsWgPerCu : kRowsWgPerC
   if (tile >= end) return;
 
   float2 twb[16];
-  if constexpr (kDoubleBufferRows && !COLS) {
-    // rows: register double buffering, the loads of the next tile are in
-    // flight while this tile is transformed
-    float2 va[kP], vb[kP];
-    TileId ta = tile_pencil<COLS>(tile, w, W, npen, p.O, p.S);
-    load_tile<L, MIN>(va, p, in, ta, jt);
-    for (;;) {
-      const long long nxt = tile + nwg_x;
-      const bool more = nxt < end;
-      TileId tb;
-      if (more) {
-        tb = tile_pencil<COLS>(nxt, w, W, npen, p.O, p.S);
-        load_tile<L, MIN>(vb, p, in, tb, jt);
-      }
-      stages_from<L, W, COLS, SPLIT, 0>(va, twb, lds, p, jt, w);
-      store_tile<L, MOUT>(va, p, out, ta, jt);
-      if (!more) break;
-#pragma unroll
-      for (int i = 0; i < kP; ++i) va[i] = vb[i];
-      ta = tb;
-      tile = nxt;
-    }
-  } else {
-    // column tiles: one register set
-    float2 va[kP];
-    for (; tile < end; tile += nwg_x) {
-      TileId ta = tile_pencil<COLS>(tile, w, W, npen, p.O, p.S);
-      load_tile<L, MIN>(va, p, in, ta, jt);
-      stages_from<L, W, COLS, SPLIT, 0>(va, twb, lds, p, jt, w);
-      store_tile<L, MOUT>(va, p, out, ta, jt);
-    }
+  float2 va[kP];
+  for (; tile < end; tile += nwg_x) {
+    const TileId ta = tile_of<W>(tile, p.O, p.S);
+    load_tile<L, COLS, MIN>(va, p, in, ta, w, jt);
+    stages_from<L, W, COLS, SPLIT, 0>(va, twb, lds, p, jt, w);
+    store_tile<L, COLS, MOUT>(va, p, out, ta, w, jt);
   }
 }
 

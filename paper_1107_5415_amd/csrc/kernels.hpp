@@ -26,8 +26,10 @@ const char* mfma_kernel_name(const PassDesc& p);
 
 // One phase of the batched persistent launch (tile_lg 11..13: tiles of
 // 2^tile_lg elements, 2^tile_lg / 16 threads per workgroup).  qbeg[0..8]
-// bounds the eight queues of the phase in `items`; heads[0..7] must be zero
-// (launch_batch_clear) before the launch.
+// bounds the eight queues of the phase in `items`; the heads
+// heads[kHeadStride * q], q < 8, must be zero (launch_batch_clear) before the
+// launch.
+constexpr int kHeadStride = 32;
 hipError_t launch_batch(int tile_lg, const BatchPass* passes, const int2* items, const int* qbeg,
                         int* heads, const float2* in, float2* out, float2* ws, int grid,
                         hipStream_t s);

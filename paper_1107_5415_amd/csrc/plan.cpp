@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "ktrace.hpp"
 
@@ -22,6 +23,9 @@ namespace {
 constexpr i64 kMaxPencil = 8192;   // longest digit handled on chip
 constexpr i64 kMaxTile = 8192;     // elements of one single-pass tile
 constexpr i64 kTileTarget = 4096;  // elements per tile for short pencils
+// pyramid levels whose channel (all signals) has at most this many points
+// run their channel FFTs in one batched launch
+constexpr i64 kChannelBatchElems = i64(1) << 19;
 
 Vec4 zero4() { return Vec4{0, 0, 0, 0}; }
 
@@ -355,7 +359,11 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
         pd.split = ((i64)Wc * pd.L * 17 / 16 * 8 > 72 * 1024) ? 1 : 0;
       }
       if ((i64)pd.W * pd.L / pd.P > 1024) pd.kind = 0;
-      if (pd.kind == 1 && R.b - R.a == 1 && stream_supported(pd.L, pd.W, pd.S > 1)) pd.kind = 2;
+      // the streaming kernel assumes full tiles inside one signal and
+      // 32-bit element offsets
+      if (pd.kind == 1 && R.b - R.a == 1 && stream_supported(pd.L, pd.W, pd.S > 1) &&
+          ((i64)pd.O * pd.S) % pd.W == 0 && p->m < (i64(1) << 28))
+        pd.kind = 2;
     }
     pd.nst = 0;
     for (int g = R.a; g < R.b; ++g) {
@@ -784,8 +792,27 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
     }
     size_t fws = w->fftM->ws_elems;
     for (auto& L : w->lv) fws = std::max(fws, L.fftN->ws_elems);
-    // F0 (m), F1 (m/2), D2 (m/2), FFT workspace
-    w->ws_elems = (size_t)(batch * w->m) * 2 + fws;
+    // small levels: batch * m_l / 2 at most kChannelBatchElems points
+    w->small_from = levels;
+    while (w->small_from > 0 &&
+           batch * (w->lv[w->small_from - 1].ml / 2) <= kChannelBatchElems)
+      --w->small_from;
+    size_t chan_ws = 0;
+    w->stage_lvl.assign(levels, 0);
+    if (w->small_from < levels) {
+      i64 o = 0;
+      for (int l = w->small_from; l < levels; ++l) {
+        w->stage_lvl[l] = o;
+        o += batch * (w->lv[l].ml / 2);
+      }
+      w->stage_d1 = o;
+      o += batch * (w->lv[levels - 1].ml / 2);
+      w->stage_elems = (size_t)o;
+      chan_ws = (size_t)o;   // one workspace slot per channel signal
+    }
+    w->fw_elems = std::max(fws, chan_ws);
+    // F0 (m), F1 (m/2), D2 (m/2), FW = FFT workspace, staging
+    w->ws_elems = (size_t)(batch * w->m) * 2 + w->fw_elems + w->stage_elems;
   } catch (const StatusError&) {
     free_wave_plan(w);
     throw;
@@ -802,9 +829,48 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
   return w;
 }
 
+namespace {
+// Batched channel plans: one lattice per (small level, signal) and one per
+// signal for the final low-pass channel.  dec: staging -> coefficients
+// (inverse FFTs), rec: coefficients -> staging (forward FFTs).
+void build_channel_batches(WavePlan* w) {
+  if (w->small_from >= w->levels) return;
+  const int d = w->d;
+  const i64 B = w->batch;
+  std::vector<i64> Ms, st, co, wo;
+  i64 coff = 0;
+  std::vector<i64> coeff_off(w->levels + 1, 0);
+  for (int l = 0; l < w->levels; ++l) {
+    coeff_off[l] = coff;
+    coff += w->lv[l].ml / 2;
+  }
+  coeff_off[w->levels] = coff;
+  i64 wsx = 0;
+  auto add = [&](const Mat& N, i64 half, i64 stage, i64 cblock) {
+    for (i64 b = 0; b < B; ++b) {
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) Ms.push_back(N.a[i][j]);
+      st.push_back(stage + b * half);
+      co.push_back(b * w->m + cblock);
+      wo.push_back(wsx);
+      wsx += half;
+    }
+  };
+  for (int l = w->small_from; l < w->levels; ++l)
+    add(w->lv[l].Nl, w->lv[l].ml / 2, w->stage_lvl[l], coeff_off[l]);
+  add(w->lv[w->levels - 1].Nl, w->lv[w->levels - 1].ml / 2, w->stage_d1, coeff_off[w->levels]);
+  const int count = (int)st.size();
+  w->chan_dec = build_batch_plan_at(count, d, Ms.data(), st.data(), co.data(), wo.data(),
+                                    (size_t)wsx, 0, 12, 0);
+  w->chan_rec = build_batch_plan_at(count, d, Ms.data(), co.data(), st.data(), wo.data(),
+                                    (size_t)wsx, 0, 12, 0);
+}
+}  // namespace
+
 void upload_wave_plan(WavePlan* w) {
   upload_plan(w->fftM);
   for (auto& L : w->lv) upload_plan(L.fftN);
+  if (!w->chan_dec) build_channel_batches(w);
   if (!w->dtab) {
     w->dtab = upload_blob(w->blob);
     uintptr_t base = reinterpret_cast<uintptr_t>(w->dtab);
@@ -814,6 +880,8 @@ void upload_wave_plan(WavePlan* w) {
 
 void free_wave_plan(WavePlan* w) {
   if (!w) return;
+  free_batch_plan(w->chan_dec);
+  free_batch_plan(w->chan_rec);
   free_plan(w->fftM);
   for (auto& L : w->lv) free_plan(L.fftN);
   if (w->dtab) (void)hipFree(w->dtab);

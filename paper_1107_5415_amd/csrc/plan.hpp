@@ -115,6 +115,8 @@ struct WaveLevel {
   SplitDesc sd{};
 };
 
+struct BatchPlan;
+
 struct WavePlan {
   int d = 0;
   Mat M, J;
@@ -126,6 +128,18 @@ struct WavePlan {
   Blob blob;
   void* dtab = nullptr;
   size_t ws_elems = 0;
+  // Channel FFTs of the small levels (small_from .. levels-1, and the final
+  // low-pass channel) run as one batched launch: the splits leave their
+  // Fourier channels in a staging area of the workspace, one inverse batched
+  // launch writes them to the coefficients (and a forward one reads them back
+  // for the reconstruction).  small_from == levels: no batching.
+  int small_from = 0;
+  BatchPlan* chan_dec = nullptr;
+  BatchPlan* chan_rec = nullptr;
+  std::vector<i64> stage_lvl;   // staging offset of level l's d2hat ([B][m_l/2])
+  i64 stage_d1 = 0;             // staging offset of the final d1hat
+  size_t fw_elems = 0;          // FFT workspace region
+  size_t stage_elems = 0;
 };
 
 WavePlan* build_wave_plan(int d, const i64* M, const i64* J, int levels, i64 batch, uint32_t flags);

@@ -11,6 +11,7 @@
 //              level, [B][m_l/2] twice per level.
 #include "wave.hpp"
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "ktrace.hpp"
 
@@ -26,6 +27,7 @@ struct Bufs {
   float2* F1;
   float2* D2;
   float2* FW;
+  float2* ST;   // staging of the batched small-level channels
 };
 
 Bufs carve(const WavePlan* w, void* ws) {
@@ -36,8 +38,14 @@ Bufs carve(const WavePlan* w, void* ws) {
   b.F1 = base + bm;
   b.D2 = base + bm + bm / 2;
   b.FW = base + 2 * bm;
+  b.ST = b.FW + w->fw_elems;
   return b;
 }
+
+// Ping-pong buffer written by level l of an inverse pyramid walk (levels
+// L-1 .. 0): level 0 writes F0 and reads F1, and consecutive levels alternate,
+// so a level never writes the buffer it reads.
+float2* synth_target(const Bufs& b, int l) { return (l == 0 || l % 2 == 0) ? b.F0 : b.F1; }
 
 // algorithmic bytes of one split/unsplit level: read 8 B and write 8 B per
 // complex point and batch element, plus 4 B of mask per point
@@ -64,26 +72,38 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
   // Fourier data of level l lives in `cur` with batch stride m_l
   float2* cur = saved ? saved : b.F0;
   exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
+  const bool batched = w->chan_dec != nullptr;
   long long soff = 0;
   for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;
+    const bool small = batched && l >= w->small_from;
     float2* next;
     if (saved && l + 1 < L) {
       next = saved + soff + B * V.ml;
+    } else if (small && l + 1 == L) {
+      next = b.ST + w->stage_d1;
     } else {
       next = (cur == b.F0) ? b.F1 : b.F0;
     }
+    float2* d2 = small ? b.ST + w->stage_lvl[l] : b.D2;
     {
       TraceScope ts("split_kernel", split_bytes(B, V.ml), s);
-      check(launch_split(V.sd, B, cur, V.ml, masks[l], next, b.D2, half, s));
+      check(launch_split(V.sd, B, cur, V.ml, masks[l], next, d2, half, s));
     }
-    exec_lattice(V.fftN, true, false, false, b.D2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
+    if (!small)
+      exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
     soff += B * V.ml;
     cur = next;
   }
-  const WaveLevel& VL = w->lv[L - 1];
-  exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset(w, L), b.FW, VL.ml / 2, m, s);
+  if (batched) {
+    // every small channel and the final low-pass channel in one launch pair
+    exec_batch(w->chan_dec, true, BATCH_PERSISTENT, b.ST, coeffs, b.FW, s);
+  } else {
+    const WaveLevel& VL = w->lv[L - 1];
+    exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset(w, L), b.FW, VL.ml / 2, m,
+                 s);
+  }
 }
 
 void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* const* masks,
@@ -101,21 +121,38 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     }
   }
   const WaveLevel& VL = w->lv[L - 1];
-  // ping-pong parity chosen so that level 0 reads F1 and writes F0
-  float2* cur = saved ? saved + soff[L - 1] : (((L - 1) % 2 == 0) ? b.F1 : b.F0);
-  exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset(w, L), cur, b.FW, m, VL.ml / 2, s);
+  // the batched channel launch is used without `saved` (the autograd path
+  // keeps every level's Fourier data in `saved` instead)
+  const bool batched = w->chan_rec != nullptr && !saved;
+  float2* cur;
+  if (saved) {
+    cur = saved + soff[L - 1];
+  } else if (batched) {
+    cur = b.ST + w->stage_d1;
+  } else {
+    // level L-1 reads the buffer level L would have written
+    cur = synth_target(b, L);
+  }
+  if (batched) {
+    exec_batch(w->chan_rec, false, BATCH_PERSISTENT, coeffs, b.ST, b.FW, s);
+  } else {
+    exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset(w, L), cur, b.FW, m,
+                 VL.ml / 2, s);
+  }
   for (int l = L - 1; l >= 0; --l) {
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;
-    float2* d2 = saved ? saved + soff[l] + B * half : b.D2;
-    exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), d2, b.FW, m, half, s);
+    const bool small = batched && l >= w->small_from;
+    float2* d2 = saved ? saved + soff[l] + B * half : (small ? b.ST + w->stage_lvl[l] : b.D2);
+    if (!small)
+      exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), d2, b.FW, m, half, s);
     float2* next;
     if (l == 0) {
       next = b.F0;
     } else if (saved) {
       next = saved + soff[l - 1];
     } else {
-      next = (cur == b.F0) ? b.F1 : b.F0;
+      next = synth_target(b, l);
     }
     {
       TraceScope ts("unsplit_kernel", split_bytes(B, V.ml), s);
