@@ -86,6 +86,19 @@ enum BatchVariant : int {
   BATCH_COLS_IN = 4,          // strided pencils, grid in, natural out
 };
 
+// floor(n / d) for 0 <= n < 2^31 as (n * mag) >> (31 + sh), with
+// sh = ceil(log2 d) and mag = floor(2^(31 + sh) / d) + 1 < 2^32 (division by
+// an invariant integer through multiplication; the rounding error of the
+// scaled reciprocal stays below 1/d for n < 2^31).
+struct FastDiv {
+  unsigned mag;
+  int sh;
+};
+
+__host__ __device__ __forceinline__ unsigned fast_div(unsigned n, FastDiv f) {
+  return (unsigned)(((unsigned long long)n * f.mag) >> (31 + f.sh));
+}
+
 // One level of the Fourier-domain wavelet split (natural orders).
 struct SplitDesc {
   long long mM;               // |det M_l| (points of the level)
@@ -99,6 +112,11 @@ struct SplitDesc {
   int w[4];                   // phase weights: phi(h) = exp(-2 pi i (w.h mod E)/E)
   int E;                      // phase modulus (largest elementary divisor of M_l)
   const float2* tw;           // exp(-2 pi i t / E), t in [0, E)
+  // 32-bit index path (every intermediate of the fiber maps below 2^30 in
+  // magnitude, checked on the host): divisions by the box diagonals and by E
+  // through FastDiv
+  int narrow;
+  FastDiv fKN[4], fHM[4], fE;
 };
 
 }  // namespace lfft

@@ -659,6 +659,21 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
 // Wavelet plans (Section 5.3)
 
 namespace {
+// Multiply-shift division by d (1 <= d < 2^31); checked on boundary values.
+FastDiv make_fast_div(i64 d) {
+  if (d < 1 || d >= (i64(1) << 31)) throw StatusError{E_STATE};
+  int sh = 0;
+  while ((i64(1) << sh) < d) ++sh;
+  const unsigned long long mag = ((1ull << (31 + sh)) / (unsigned long long)d) + 1;
+  if (mag >> 32) throw StatusError{E_STATE};
+  FastDiv f{(unsigned)mag, sh};
+  const i64 top = (i64(1) << 31) - 1;
+  const i64 probes[] = {0, 1, d - 1, d, d + 1, top, top - 1, (top / d) * d, (top / d) * d - 1};
+  for (i64 n : probes)
+    if (n >= 0 && n <= top && (i64)fast_div((unsigned)n, f) != n / d) throw StatusError{E_STATE};
+  return f;
+}
+
 // (g0, y0 numerators, v) for |det J| = 2: g0 a unit vector outside J^T Z^d,
 // y0 = num/2 the non-zero point of P(J) in [-1/2, 1/2)^d, v = J y0.
 void dilation_data(const Mat& J, Vec4& g0, Vec4& v) {
@@ -787,6 +802,33 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
       }
       sd.E = (int)E;
       sd.tw = tw.table(E);
+      // 32-bit index path: bound every intermediate of the fiber maps.  The
+      // reduction starts from k (< KN) or h0 + s (< 2 HM_ii per coordinate);
+      // reducing coordinate i subtracts q_i * column i with
+      // |q_i| <= bound_i / HM_ii + 1 from the coordinates above it.
+      {
+        const i64 lim = i64(1) << 30;
+        std::vector<i64> bnd(d);
+        for (int i = 0; i < d; ++i) bnd[i] = std::max<i64>(HN.a[i][i], 2 * HMt.a[i][i]);
+        bool ok = L.ml < (i64(1) << 28);
+        for (int i = d - 1; i >= 0 && ok; --i) {
+          const i64 q = bnd[i] / HMt.a[i][i] + 1;
+          for (int r = 0; r < i; ++r) {
+            bnd[r] += q * HMt.a[r][i];
+            if (bnd[r] >= lim) ok = false;
+          }
+          bnd[i] = HMt.a[i][i];
+        }
+        i64 hsum = 0;
+        for (int i = 0; i < d; ++i) hsum += HMt.a[i][i];
+        if (hsum * E >= (i64(1) << 31)) ok = false;
+        sd.narrow = ok ? 1 : 0;
+        for (int i = 0; i < 4; ++i) {
+          sd.fKN[i] = make_fast_div(i < d ? sd.KN[i] : 1);
+          sd.fHM[i] = make_fast_div(i < d ? HMt.a[i][i] : 1);
+        }
+        sd.fE = make_fast_div(E);
+      }
       w->lv.push_back(L);
       Ml = L.Nl;
     }

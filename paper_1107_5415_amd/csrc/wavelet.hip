@@ -72,12 +72,65 @@ __device__ __forceinline__ Fiber fiber_of(const SplitDesc& sd, long long klin) {
   return f;
 }
 
+// 32-bit fiber maps (sd.narrow): the same arithmetic with invariant-divisor
+// multiplications instead of 64-bit divisions.
+__device__ __forceinline__ void reduce_hm32(const SplitDesc& sd, int* v) {
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    if (i < sd.d) {
+      // floor(v / h) for |v| < 2^30 (bounded on the host)
+      const int h = sd.HM[i][i];
+      const int x = v[i];
+      const int q = x >= 0 ? (int)fast_div((unsigned)x, sd.fHM[i])
+                           : -(int)fast_div((unsigned)(h - 1 - x), sd.fHM[i]);
+#pragma unroll
+      for (int r = 0; r <= i; ++r) v[r] -= q * sd.HM[r][i];
+    }
+  }
+}
+
+__device__ __forceinline__ Fiber fiber_of32(const SplitDesc& sd, long long klin) {
+  int k[4] = {0, 0, 0, 0};
+  unsigned r = (unsigned)klin;
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    if (i < sd.d) {
+      const unsigned q = fast_div(r, sd.fKN[i]);
+      k[i] = (int)(r - q * (unsigned)sd.KN[i]);
+      r = q;
+    }
+  }
+  int h0[4] = {k[0], k[1], k[2], k[3]};
+  reduce_hm32(sd, h0);
+  int h1[4] = {h0[0] + sd.s[0], h0[1] + sd.s[1], h0[2] + sd.s[2], h0[3] + sd.s[3]};
+  reduce_hm32(sd, h1);
+  int i0 = 0, i1 = 0, acc = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i < sd.d) {
+      i0 += h0[i] * (int)sd.hstride[i];
+      i1 += h1[i] * (int)sd.hstride[i];
+      acc += h0[i] * sd.w[i];
+    }
+  }
+  const unsigned q = fast_div((unsigned)acc, sd.fE);
+  Fiber f;
+  f.i0 = i0;
+  f.i1 = i1;
+  f.phi = sd.tw[(unsigned)acc - q * (unsigned)sd.E];
+  return f;
+}
+
+__device__ __forceinline__ Fiber fiber_at(const SplitDesc& sd, long long k) {
+  return sd.narrow ? fiber_of32(sd, k) : fiber_of(sd, k);
+}
+
 __global__ void split_kernel(SplitDesc sd, long long batch, const float2* __restrict__ ah,
                              long long ah_bs, const float* __restrict__ mask, float2* __restrict__ d1,
                              float2* __restrict__ d2, long long d_bs) {
   long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
-  Fiber f = fiber_of(sd, k);
+  Fiber f = fiber_at(sd, k);
   const float a0 = mask[f.i0] * kInvSqrt2, a1 = mask[f.i1] * kInvSqrt2;
   const float2 cphi = cconj(f.phi);
   for (long long b = 0; b < batch; ++b) {
@@ -94,7 +147,7 @@ __global__ void unsplit_kernel(SplitDesc sd, long long batch, const float2* __re
                                long long ah_bs) {
   long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
-  Fiber f = fiber_of(sd, k);
+  Fiber f = fiber_at(sd, k);
   const float a0 = mask[f.i0] * kInvSqrt2, a1 = mask[f.i1] * kInvSqrt2;
   for (long long b = 0; b < batch; ++b) {
     float2 y1 = d1[b * d_bs + k];
@@ -113,7 +166,7 @@ __global__ void split_mask_grad_kernel(SplitDesc sd, long long batch, const floa
                                        float* __restrict__ gmask) {
   long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
-  Fiber f = fiber_of(sd, k);
+  Fiber f = fiber_at(sd, k);
   const float2 c = cconj(f.phi);
   float s0 = 0.f, s1 = 0.f;
   for (long long b = 0; b < batch; ++b) {
@@ -135,7 +188,7 @@ __global__ void unsplit_mask_grad_kernel(SplitDesc sd, long long batch, const fl
                                          float* __restrict__ gmask) {
   long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (k >= sd.mN) return;
-  Fiber f = fiber_of(sd, k);
+  Fiber f = fiber_at(sd, k);
   float s0 = 0.f, s1 = 0.f;
   for (long long b = 0; b < batch; ++b) {
     float2 y1 = d1[b * d_bs + k];
