@@ -62,13 +62,30 @@ def traffic(fetch_csv, write_csv, kernel, copy_kib, alg_bytes, sources, cmd_f, c
     fe = _per_dispatch(fetch_csv, "FETCH_SIZE")
     wr = _per_dispatch(write_csv, "WRITE_SIZE")
 
-    def find(d, key):
-        hits = [k for k in d if key in k]
+    def bare(name):
+        # "void ns::kernel<args>(params)" -> "kernel<args>"
+        n = name.replace("lfft::(anonymous namespace)::", "").replace("lfft::", "")
+        if n.startswith("void "):
+            n = n[5:]
+        depth = 0
+        for i, ch in enumerate(n):
+            if ch == "<":
+                depth += 1
+            elif ch == ">":
+                depth -= 1
+            elif ch == "(" and depth == 0:
+                return n[:i].strip()
+        return n.strip()
+
+    def find(d, key, exact=True):
+        hits = [k for k in d if (bare(k) == key if exact else key in k)]
         if len(hits) != 1:
             raise SystemExit("kernel %r matched %d names" % (key, len(hits)))
         return d[hits[0]]
-    cf = statistics.median(find(fe, COPY_KERNEL))
-    cw = statistics.median(find(wr, COPY_KERNEL))
+    # the calibration copy is the largest device copy of the run (the other
+    # copies are small host-to-device uploads of inputs and masks)
+    cf = max(find(fe, COPY_KERNEL, exact=False))
+    cw = max(find(wr, COPY_KERNEL, exact=False))
     sf = copy_kib / cf
     sw = copy_kib / cw
     # mean over the kernel's dispatches: the same launch mix as the
