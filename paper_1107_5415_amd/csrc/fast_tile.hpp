@@ -69,6 +69,9 @@ __device__ __forceinline__ void addr_init(Addr<MODE>& A, const MapDesc& m, const
     if (m.d == 2) {
       gadd2(m, A.cbase[0], A.cbase[1], m.To[pc.o]);
       gadd2(m, A.cbase[0], A.cbase[1], m.Ts[pc.s]);
+    } else if (m.d == 3) {
+      gadd3(m, A.cbase, m.To[pc.o]);
+      gadd3(m, A.cbase, m.Ts[pc.s]);
     } else {
       gadd32(m, A.cbase, m.To[pc.o]);
       gadd32(m, A.cbase, m.Ts[pc.s]);
@@ -97,6 +100,14 @@ __device__ __forceinline__ void for_positions(const Addr<MODE>& A, const MapDesc
       for (int i = 0; i < R; ++i) {
         f(i, c0 * h11 + c1);
         if (i + 1 < R) gadd2(m, c0, c1, D);
+      }
+    } else if (m.d == 3) {
+      int c[4] = {A.cbase[0], A.cbase[1], A.cbase[2], 0};
+      gadd3(m, c, m.Tl[l0]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        f(i, nat_index3(m, c));
+        if (i + 1 < R) gadd3(m, c, D);
       }
     } else {
       int c[4] = {A.cbase[0], A.cbase[1], A.cbase[2], A.cbase[3]};

@@ -233,6 +233,32 @@ __device__ __forceinline__ void gadd2(const MapDesc& m, int& c0, int& c1, int4 b
   c0 -= c0 >= m.H[0][0] ? m.H[0][0] : 0;
 }
 
+// Natural box of a 3-D lattice (upper-triangular H): c += b for reduced c
+// and b.  Coordinate 2 needs at most one subtraction of column 2, which
+// leaves coordinate 1 in (-h11, 2 h11 - 1): one correction by column 1;
+// coordinate 0 then lies in (-2 h00, 3 h00 - 2): at most two corrections.
+__device__ __forceinline__ void gadd3(const MapDesc& m, int* c, int4 b) {
+  c[0] += b.x;
+  c[1] += b.y;
+  c[2] += b.z;
+  const bool o2 = c[2] >= m.H[2][2];
+  c[2] -= o2 ? m.H[2][2] : 0;
+  c[1] -= o2 ? m.H[1][2] : 0;
+  c[0] -= o2 ? m.H[0][2] : 0;
+  const bool u1 = c[1] < 0, o1 = c[1] >= m.H[1][1];
+  c[1] += u1 ? m.H[1][1] : (o1 ? -m.H[1][1] : 0);
+  c[0] += u1 ? m.H[0][1] : (o1 ? -m.H[0][1] : 0);
+  const int h00 = m.H[0][0];
+  c[0] += c[0] < 0 ? h00 : 0;
+  c[0] += c[0] < 0 ? h00 : 0;
+  c[0] -= c[0] >= h00 ? h00 : 0;
+  c[0] -= c[0] >= h00 ? h00 : 0;
+}
+
+__device__ __forceinline__ int nat_index3(const MapDesc& m, const int* c) {
+  return c[0] * (int)m.box_stride[0] + c[1] * (int)m.box_stride[1] + c[2];
+}
+
 // linear natural index (int: the planner keeps these lattices below 2^30 points)
 __device__ __forceinline__ int nat_index_i(const MapDesc& m, const int* c) {
   int idx = 0;

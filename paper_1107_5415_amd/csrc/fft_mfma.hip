@@ -203,6 +203,18 @@ __device__ __forceinline__ long long side_index(const MapDesc& m, long long b, i
     return b * m.bstride + (long long)m.To[o].x + (long long)m.Tl[l].x + (long long)m.Ts[s].x;
   } else {
     int c[4] = {0, 0, 0, 0};
+    if (m.d == 2) {
+      gadd2(m, c[0], c[1], m.To[o]);
+      gadd2(m, c[0], c[1], m.Tl[l]);
+      gadd2(m, c[0], c[1], m.Ts[s]);
+      return b * m.bstride + c[0] * m.H[1][1] + c[1];
+    }
+    if (m.d == 3) {
+      gadd3(m, c, m.To[o]);
+      gadd3(m, c, m.Tl[l]);
+      gadd3(m, c, m.Ts[s]);
+      return b * m.bstride + nat_index3(m, c);
+    }
     gadd32(m, c, m.To[o]);
     gadd32(m, c, m.Tl[l]);
     gadd32(m, c, m.Ts[s]);

@@ -85,6 +85,9 @@ __device__ __forceinline__ void side_init(Side<MODE>& A, const MapDesc& m, const
     if (m.d == 2) {
       gadd2(m, A.c[0], A.c[1], m.To[o]);
       gadd2(m, A.c[0], A.c[1], m.Ts[s]);
+    } else if (m.d == 3) {
+      gadd3(m, A.c, m.To[o]);
+      gadd3(m, A.c, m.Ts[s]);
     } else {
       gadd32(m, A.c, m.To[o]);
       gadd32(m, A.c, m.Ts[s]);
@@ -114,6 +117,14 @@ __device__ __forceinline__ void side_positions(const Side<MODE>& A, const MapDes
       for (int i = 0; i < R; ++i) {
         f(i, c0 * h11 + c1);
         if (i + 1 < R) gadd2(m, c0, c1, D);
+      }
+    } else if (m.d == 3) {
+      int c[4] = {A.c[0], A.c[1], A.c[2], 0};
+      gadd3(m, c, m.Tl[l0]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        f(i, nat_index3(m, c));
+        if (i + 1 < R) gadd3(m, c, D);
       }
     } else {
       int c[4] = {A.c[0], A.c[1], A.c[2], A.c[3]};
