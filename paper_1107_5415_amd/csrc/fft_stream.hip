@@ -449,14 +449,15 @@ bool stream_supported(int L, int W, bool cols) {
     return (L == 8192 && W == 1) || (L == 4096 && W == 1) || (L == 2048 && W == 2) ||
            (L == 1024 && W == 4) || (L == 512 && W == 8) || (L == 256 && W == 16);
   }
-  return (L == 2048 && W == 8) || (L == 1024 && W == 16) || (L == 512 && W == 32) ||
-         (L == 256 && W == 64) || (L == 4096 && W == 4);
+  return (L == 4096 && W == 4) || (L == 2048 && W == 8) || (L == 1024 && (W == 16 || W == 8)) ||
+         (L == 512 && (W == 32 || W == 16 || W == 8)) ||
+         (L == 256 && (W == 64 || W == 32 || W == 16 || W == 8));
 }
 
 const char* stream_kernel_name(const PassDesc& p) {
   // the template arguments exactly as the profiler prints the symbol
   const bool cols = p.S > 1;
-  const int W = cols ? (p.L == 4096 ? 4 : 16384 / p.L) : (p.L >= 4096 ? 1 : 4096 / p.L);
+  const int W = p.W;
   const bool split = (cols || kSplitRows) ? ((long long)W * p.L * 17 / 16 * 8 > 72 * 1024 || kSplitRows)
                                           : false;
   const int min = p.in.mode == MAP_NATURAL ? 2 : 0;
@@ -478,12 +479,18 @@ hipError_t launch_stream_pass(const PassDesc& p, const float2* in, float2* out, 
       default: return hipErrorInvalidValue;
     }
   }
-  switch (p.L) {
-    case 4096: return launch_i<4096, 4, true>(p, in, out, s);
-    case 2048: return launch_i<2048, 8, true>(p, in, out, s);
-    case 1024: return launch_i<1024, 16, true>(p, in, out, s);
-    case 512: return launch_i<512, 32, true>(p, in, out, s);
-    case 256: return launch_i<256, 64, true>(p, in, out, s);
+  switch (p.L * 100 + p.W) {
+    case 4096 * 100 + 4: return launch_i<4096, 4, true>(p, in, out, s);
+    case 2048 * 100 + 8: return launch_i<2048, 8, true>(p, in, out, s);
+    case 1024 * 100 + 16: return launch_i<1024, 16, true>(p, in, out, s);
+    case 1024 * 100 + 8: return launch_i<1024, 8, true>(p, in, out, s);
+    case 512 * 100 + 32: return launch_i<512, 32, true>(p, in, out, s);
+    case 512 * 100 + 16: return launch_i<512, 16, true>(p, in, out, s);
+    case 512 * 100 + 8: return launch_i<512, 8, true>(p, in, out, s);
+    case 256 * 100 + 64: return launch_i<256, 64, true>(p, in, out, s);
+    case 256 * 100 + 32: return launch_i<256, 32, true>(p, in, out, s);
+    case 256 * 100 + 16: return launch_i<256, 16, true>(p, in, out, s);
+    case 256 * 100 + 8: return launch_i<256, 8, true>(p, in, out, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -315,6 +315,10 @@ void tiled_schedule(LatticePlan* p) {
   }
 }
 
+i64 batch_pencils(const LatticePlan* p, const PassDesc& pd) {
+  return p->batch * (i64)pd.O * pd.S;
+}
+
 void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& out_side, int sign,
                   TwCache& tw) {
   E.sign = sign;
@@ -352,8 +356,13 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
         pd.W = (int)std::max<i64>(1, 4096 / pd.L);
         pd.split = 0;
       } else {
+        // widest column tile that divides S and fits 16384 elements; passes
+        // with fewer than 512 such tiles get narrower tiles (down to 8
+        // columns, whole 64-byte segments) so that every CU has work
+        const i64 npen = batch_pencils(p, pd);
         int Wc = 64;
         while (Wc > 1 && (pd.S % Wc != 0 || (i64)Wc * pd.L > 16384)) Wc /= 2;
+        while (Wc > 8 && npen / Wc < 512) Wc /= 2;
         pd.W = Wc;
         pd.P = 16;
         pd.split = ((i64)Wc * pd.L * 17 / 16 * 8 > 72 * 1024) ? 1 : 0;
@@ -853,8 +862,18 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
       chan_ws = (size_t)o;   // one workspace slot per channel signal
     }
     w->fw_elems = std::max(fws, chan_ws);
-    // F0 (m), F1 (m/2), D2 (m/2), FW = FFT workspace, staging
-    w->ws_elems = (size_t)(batch * w->m) * 2 + w->fw_elems + w->stage_elems;
+    w->big_d2.assign(levels, 0);
+    w->bd_elems = 0;
+    size_t fws2 = 0;
+    for (int l = 0; l < w->small_from; ++l) {
+      w->big_d2[l] = (i64)w->bd_elems;
+      w->bd_elems += (size_t)(batch * (w->lv[l].ml / 2));
+      fws2 = std::max(fws2, w->lv[l].fftN->ws_elems);
+    }
+    w->fw2_elems = fws2;
+    // F0 (m), F1 (m/2), D2 (m/2), FW, staging, BD, FW2
+    w->ws_elems = (size_t)(batch * w->m) * 2 + w->fw_elems + w->stage_elems + w->bd_elems +
+                  w->fw2_elems;
   } catch (const StatusError&) {
     free_wave_plan(w);
     throw;
@@ -913,6 +932,17 @@ void upload_wave_plan(WavePlan* w) {
   upload_plan(w->fftM);
   for (auto& L : w->lv) upload_plan(L.fftN);
   if (!w->chan_dec) build_channel_batches(w);
+  if (!w->s2) {
+    if (hipStreamCreateWithFlags(&w->s2, hipStreamNonBlocking) != hipSuccess) {
+      w->s2 = nullptr;
+      throw StatusError{E_HIP};
+    }
+    w->ev.assign(w->levels, nullptr);
+    for (auto& e : w->ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) throw StatusError{E_HIP};
+    if (hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming) != hipSuccess)
+      throw StatusError{E_HIP};
+  }
   if (!w->dtab) {
     w->dtab = upload_blob(w->blob);
     uintptr_t base = reinterpret_cast<uintptr_t>(w->dtab);
@@ -922,6 +952,10 @@ void upload_wave_plan(WavePlan* w) {
 
 void free_wave_plan(WavePlan* w) {
   if (!w) return;
+  for (auto e : w->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (w->ev_join) (void)hipEventDestroy(w->ev_join);
+  if (w->s2) (void)hipStreamDestroy(w->s2);
   free_batch_plan(w->chan_dec);
   free_batch_plan(w->chan_rec);
   free_plan(w->fftM);

@@ -138,8 +138,18 @@ struct WavePlan {
   BatchPlan* chan_rec = nullptr;
   std::vector<i64> stage_lvl;   // staging offset of level l's d2hat ([B][m_l/2])
   i64 stage_d1 = 0;             // staging offset of the final d1hat
-  size_t fw_elems = 0;          // FFT workspace region
+  size_t fw_elems = 0;          // FFT workspace region (main stream)
   size_t stage_elems = 0;
+  // The channel FFTs of the large levels (0 .. small_from-1) run on a second
+  // stream, overlapping the chain of splits (decomposition) or ahead of the
+  // unsplits (reconstruction); each has its own d2hat buffer, and the two
+  // streams use separate FFT workspaces.
+  std::vector<i64> big_d2;      // offset of level l's d2hat in the BD region
+  size_t bd_elems = 0;          // BD region
+  size_t fw2_elems = 0;         // FFT workspace of the second stream
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;   // one per level
+  hipEvent_t ev_join = nullptr;
 };
 
 WavePlan* build_wave_plan(int d, const i64* M, const i64* J, int levels, i64 batch, uint32_t flags);

@@ -28,6 +28,8 @@ struct Bufs {
   float2* D2;
   float2* FW;
   float2* ST;   // staging of the batched small-level channels
+  float2* BD;   // d2hat of the large levels (channel FFTs on the second stream)
+  float2* FW2;  // FFT workspace of the second stream
 };
 
 Bufs carve(const WavePlan* w, void* ws) {
@@ -39,7 +41,21 @@ Bufs carve(const WavePlan* w, void* ws) {
   b.D2 = base + bm + bm / 2;
   b.FW = base + 2 * bm;
   b.ST = b.FW + w->fw_elems;
+  b.BD = b.ST + w->stage_elems;
+  b.FW2 = b.BD + w->bd_elems;
   return b;
+}
+
+// s2 starts after everything enqueued on s so far (event e)
+void fork(const WavePlan* w, hipEvent_t e, hipStream_t s) {
+  check(hipEventRecord(e, s));
+  check(hipStreamWaitEvent(w->s2, e, 0));
+}
+
+// s continues after everything enqueued on s2 so far
+void join(const WavePlan* w, hipStream_t s) {
+  check(hipEventRecord(w->ev_join, w->s2));
+  check(hipStreamWaitEvent(s, w->ev_join, 0));
 }
 
 // Ping-pong buffer written by level l of an inverse pyramid walk (levels
@@ -74,6 +90,7 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
   exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
   const bool batched = w->chan_dec != nullptr;
   long long soff = 0;
+  bool forked = false;
   for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;
@@ -86,13 +103,21 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
     } else {
       next = (cur == b.F0) ? b.F1 : b.F0;
     }
-    float2* d2 = small ? b.ST + w->stage_lvl[l] : b.D2;
+    const bool big = l < w->small_from;
+    float2* d2 = small ? b.ST + w->stage_lvl[l] : (big ? b.BD + w->big_d2[l] : b.D2);
     {
       TraceScope ts("split_kernel", split_bytes(B, V.ml), s);
       check(launch_split(V.sd, B, cur, V.ml, masks[l], next, d2, half, s));
     }
-    if (!small)
+    if (big) {
+      // the channel FFT overlaps the next splits
+      fork(w, w->ev[l], s);
+      forked = true;
+      exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW2, half, m,
+                   w->s2);
+    } else if (!small) {
       exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
+    }
     soff += B * V.ml;
     cur = next;
   }
@@ -104,6 +129,7 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
     exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset(w, L), b.FW, VL.ml / 2, m,
                  s);
   }
+  if (forked) join(w, s);
 }
 
 void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* const* masks,
@@ -133,6 +159,19 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     // level L-1 reads the buffer level L would have written
     cur = synth_target(b, L);
   }
+  // large channels: forward FFTs on the second stream, issued in the order the
+  // unsplits need them (level small_from-1 first); level l's event marks its
+  // completion.  Without `saved` only.
+  const bool ahead = !saved && w->small_from > 0;
+  if (ahead) {
+    fork(w, w->ev_join, s);
+    for (int l = w->small_from - 1; l >= 0; --l) {
+      const WaveLevel& V = w->lv[l];
+      exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), b.BD + w->big_d2[l],
+                   b.FW2, m, V.ml / 2, w->s2);
+      check(hipEventRecord(w->ev[l], w->s2));
+    }
+  }
   if (batched) {
     exec_batch(w->chan_rec, false, BATCH_PERSISTENT, coeffs, b.ST, b.FW, s);
   } else {
@@ -143,8 +182,12 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;
     const bool small = batched && l >= w->small_from;
-    float2* d2 = saved ? saved + soff[l] + B * half : (small ? b.ST + w->stage_lvl[l] : b.D2);
-    if (!small)
+    const bool big = ahead && l < w->small_from;
+    float2* d2 = saved ? saved + soff[l] + B * half
+                       : (small ? b.ST + w->stage_lvl[l] : (big ? b.BD + w->big_d2[l] : b.D2));
+    if (big)
+      check(hipStreamWaitEvent(s, w->ev[l], 0));
+    else if (!small)
       exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), d2, b.FW, m, half, s);
     float2* next;
     if (l == 0) {
