@@ -138,11 +138,16 @@ __device__ __forceinline__ void stage_mfma(const StageDesc& st, const WOps& Wm, 
     bf_split<COLS>(b, W, nbl, w, bl);
     const Geo g = geo(st, bl);
     bf16x8 rh, rl, ih, il;
+    // twiddles w^i, i = 8h .. 8h+7, from two table entries: w^(8h) and w,
+    // then successive products (a few ulp, far inside this path's bound)
+    float2 tcur = twiddle(st, g.jm, 8 * h, sign);
+    const float2 tstep = twiddle(st, g.jm, 1, sign);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = 8 * h + j;
       float2 x = lds[phys(lds_pos<COLS>(g.in0 + i * g.in_step, w, W, L))];
-      if (g.jm) x = c_mul(x, twiddle(st, g.jm, i, sign));
+      x = c_mul(x, tcur);
+      tcur = c_mul(tcur, tstep);
       __bf16 a, e;
       split_bf16(x.x, a, e);
       rh[j] = a;
@@ -178,10 +183,15 @@ __device__ __forceinline__ void stage_valu(const StageDesc& st, int sign, float2
     bf_split<COLS>(b, W, nbl, w, bl);
     const Geo g = geo(st, bl);
     float2 v[R];
+    const float2 tstep = twiddle(st, g.jm, 1, sign);
+    float2 tcur = tstep;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       float2 x = lds[phys(lds_pos<COLS>(g.in0 + i * g.in_step, w, W, L))];
-      if (i > 0 && g.jm) x = c_mul(x, twiddle(st, g.jm, i, sign));
+      if (i > 0) {
+        x = c_mul(x, tcur);
+        tcur = c_mul(tcur, tstep);
+      }
       v[i] = x;
     }
     dft_pow2<R>(v, sign);
@@ -231,22 +241,32 @@ __global__ void __launch_bounds__(kNT) fft_mfma_kernel(PassDesc p, const float2*
   const long long npen = p.batch * (long long)O * S;
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   // load: element e -> (w, l); consecutive e are consecutive HBM words of
-  // the identity layout on both pencil orientations
-#pragma unroll 4
-  for (int k = 0; k < kPer; ++k) {
-    const int e = tid + kNT * k;
-    const int w = COLS ? e % W : e / L;
-    const int l = COLS ? e / W : e % L;
-    const long long pen = tile * W + w;
-    float2 v = make_float2(0.f, 0.f);
-    if (pen < npen) {
-      const long long bo = pen / S;
-      const int s = (int)(pen - bo * S);
-      const long long b = bo / O;
-      const int o = (int)(bo - b * O);
-      v = in[side_index<MIN>(p.in, b, o, l, s, L, S)];
+  // the identity layout on both pencil orientations.  All loads are issued
+  // before the first LDS write, so their latencies overlap.
+  {
+    float2 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + kNT * k;
+      const int w = COLS ? e % W : e / L;
+      const int l = COLS ? e / W : e % L;
+      const long long pen = tile * W + w;
+      v[k] = make_float2(0.f, 0.f);
+      if (pen < npen) {
+        const long long bo = pen / S;
+        const int s = (int)(pen - bo * S);
+        const long long b = bo / O;
+        const int o = (int)(bo - b * O);
+        v[k] = in[side_index<MIN>(p.in, b, o, l, s, L, S)];
+      }
     }
-    lds[phys(lds_pos<COLS>(l, w, W, L))] = v;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + kNT * k;
+      const int w = COLS ? e % W : e / L;
+      const int l = COLS ? e / W : e % L;
+      lds[phys(lds_pos<COLS>(l, w, W, L))] = v[k];
+    }
   }
   __syncthreads();
   const WOps Wm = make_w(tid & 63, p.sign);
@@ -266,7 +286,7 @@ __global__ void __launch_bounds__(kNT) fft_mfma_kernel(PassDesc p, const float2*
     __syncthreads();
   }
   // store: four-step twiddle, 1/sqrt(m) scale, scatter
-#pragma unroll 4
+#pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int e = tid + kNT * k;
     const int w = COLS ? e % W : e / L;
