@@ -52,6 +52,11 @@ CASES = [
     ("quincunx_level", ((2048, 3072), (2048, -1024)), 1),
     ("tile_ragged", ((7, 3), (0, 9)), 5),
     ("trivial_m1", ((1, 0), (0, 1)), 3),
+    ("d1_prime_997", ((997,),), 2),
+    ("d1_pow2_8192", ((8192,),), 3),
+    ("d1_four_step_2^20", ((1 << 20,),), 1),
+    ("d1_negative_mixed", ((-360,),), 2),
+    ("d1_trivial", ((1,),), 2),
 ]
 
 

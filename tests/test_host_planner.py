@@ -43,6 +43,8 @@ MATS = [
     ((2, 1, 0, 0), (0, 3, 1, 0), (1, 0, 4, 1), (0, 1, 0, 5)),
     ((1, 0), (0, 1 << 18)),
     ((8, 0), (0, 8)),
+    ((997,),),
+    ((-360,),),
 ] + [workloads.table1_matrix(i) for i in (1, 2, 0, 1024)]
 
 
