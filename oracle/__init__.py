@@ -21,6 +21,10 @@ Modules
   wavelet  Dirichlet scaling mask (Section 6.2), one-level split and its
            inverse (Section 5.3, steps 1-5), multi-level pyramid, and the
            time-domain inner-product definition it must equal
+  wavelet_q  the split for q = |det J| > 2 channels (Section 5.3 step 4 for
+           general q) with the Dirichlet mask of any q and a Householder
+           completion of the wavelet channels, its pyramid, and the
+           time-domain definition it must equal
   grad     float64 torch autograd re-implementation for gradient checks
 
 Parity status of every function is stated in its docstring; functions without
