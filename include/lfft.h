@@ -54,7 +54,8 @@ extern "C" {
 #define LFFT_E_SINGULAR (-2)     /* det M = 0                                 */
 #define LFFT_E_NOT_INTEGRAL (-3) /* J^{-1} M not integral at some level       */
 #define LFFT_E_OVERFLOW (-4)     /* exact integer work would exceed int64     */
-#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| != 2, or an
+#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, an
+                                    adjoint with |det J| > 2, or an
                                     elementary divisor with a prime factor
                                     that cannot be split to fit on chip      */
 #define LFFT_E_HIP (-6)          /* a HIP call or kernel launch failed        */
@@ -137,10 +138,18 @@ int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, u
 
 /* ---- fast wavelet decomposition (Section 5.3) --------------------------- */
 
-/* Plan `levels` dyadic steps M_1 = M, N_l = J^{-1} M_l, M_{l+1} = N_l for a
- * dilation J with |det J| = 2 (Section 5.3; Section 6.2 Dirichlet wavelets)
- * and `batch` signals.  Errors: ARG, SINGULAR, NOT_INTEGRAL, OVERFLOW,
- * UNSUPPORTED (|det J| != 2), NOMEM, HIP. */
+/* Plan `levels` steps M_1 = M, N_l = J^{-1} M_l, M_{l+1} = N_l for a
+ * dilation J with q = |det J| channels, 2 <= q <= 16 (Section 5.3, steps
+ * 1-5 for any |det J|; Section 6.2 Dirichlet wavelets for q = 2), and
+ * `batch` signals.  For q > 2 the paper defines no wavelet: the channel
+ * matrix of every fiber {k + N^T g_l : g_l in G(J^T)} (g_0 = 0, the other
+ * classes in the natural order of the Hermite box of J^T) has first row
+ * u = (a(h_l) / sqrt q)_l and the other rows from the reflection
+ * I - 2 v v^T / (v^T v), v = u + sign(u_0) e_0 (sign(0) = +1); it is
+ * orthogonal when the mask satisfies sum_l a(h_l)^2 = q.  q > 2 supports
+ * lwt_decompose / lwt_reconstruct with saved = NULL only.  Errors: ARG,
+ * SINGULAR, NOT_INTEGRAL, OVERFLOW, UNSUPPORTED (q > 16, d > 4), NOMEM,
+ * HIP. */
 int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J, int levels,
                     int64_t batch, uint32_t flags);
 int lwt_plan_destroy(lwt_plan_t plan);
@@ -150,19 +159,23 @@ int lwt_plan_destroy(lwt_plan_t plan);
 int lwt_level_info(lwt_plan_t plan, int level, int64_t* N, int64_t* m_level, int64_t* eps_N);
 
 /* Dirichlet scaling mask of level l (Section 6.2): host float[m_l] in
- * NATURAL order of G(M_l^T); values 2^{(1 + r_M - r_N)/2} on the closed
- * N_l-box of symmetric representatives, 0 elsewhere. */
+ * NATURAL order of G(M_l^T); values sqrt(q) 2^{(r_M - r_N)/2} (the quotient
+ * of the Dirichlet kernels' coefficients; 2^{(1 + r_M - r_N)/2} for q = 2) on
+ * the closed N_l-box of symmetric representatives, 0 elsewhere. */
 int lwt_dirichlet_mask(lwt_plan_t plan, int level, float* mask);
 
 /* Workspace bytes of every lwt_* execute call, and complex64 elements of
- * the `saved` buffer used for differentiation. */
+ * the `saved` buffer used for differentiation (0 for q > 2). */
 size_t lwt_workspace_size(lwt_plan_t plan);
 size_t lwt_saved_elems(lwt_plan_t plan);
 
 /* Decomposition (Section 5.3, steps 1-5, levels chained through the
  * low-pass Fourier data): samples [batch][m] NATURAL order of G(M) ->
  * coeffs [batch][m] = [d2^(1) | ... | d2^(L) | d1^(L)], block l in NATURAL
- * order of G(N_l).  masks: host array of `levels` device pointers, mask l
+ * order of G(N_l); for q > 2 the blocks of level l are its channels
+ * 1 .. q-1 (m_l / q each) and the last block is channel 0 of level L:
+ * [lvl 1: ch 1 | .. | ch q-1] .. [lvl L: ch 1 | .. | ch q-1] [ch 0].
+ * masks: host array of `levels` device pointers, mask l
  * float[m_l] in NATURAL order of G(M_l^T) (real scaling symbol; the wavelet
  * symbol is derived from it).  saved: NULL or device complex64 buffer of
  * lwt_saved_elems() receiving the per-level Fourier inputs (needed by
@@ -179,7 +192,8 @@ int lwt_reconstruct(lwt_plan_t plan, const void* coeffs, const float* const* mas
 
 /* Adjoint of lwt_decompose: grad_samples = D^H grad_coeffs, and, if
  * grad_masks (host array of device pointers) is non-NULL, d loss / d mask_l
- * summed over the batch, using `saved` from lwt_decompose. */
+ * summed over the batch, using `saved` from lwt_decompose.  q = 2 only
+ * (UNSUPPORTED otherwise), as lwt_reconstruct_backward. */
 int lwt_decompose_backward(lwt_plan_t plan, const void* grad_coeffs, const void* saved,
                            const float* const* masks, void* grad_samples, float* const* grad_masks,
                            void* workspace, hipStream_t stream);

@@ -45,6 +45,8 @@ class WaveletDecompose(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, plan, *masks):
+        if plan.q != 2:
+            raise RuntimeError("the adjoint pyramid is available for |det J| = 2 only")
         saved = plan.new_saved(x.device)
         c = plan.decompose(x.contiguous(), list(masks), saved=saved)
         ctx.plan = plan
@@ -66,6 +68,8 @@ class WaveletReconstruct(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, c, plan, *masks):
+        if plan.q != 2:
+            raise RuntimeError("the adjoint pyramid is available for |det J| = 2 only")
         saved = plan.new_saved(c.device)
         x = plan.reconstruct(c.contiguous(), list(masks), saved=saved)
         ctx.plan = plan

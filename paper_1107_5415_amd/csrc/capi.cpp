@@ -203,7 +203,7 @@ size_t lwt_saved_elems(lwt_plan_t plan) {
 
 #define LWT_CHECK(plan, ws)                                  \
   if (!plan || !plan->w) return LFFT_E_ARG;                  \
-  if (!plan->w->dtab || !plan->w->fftM->dtab) return LFFT_E_STATE; \
+  if (!plan->w->uploaded) return LFFT_E_STATE;                \
   if (!ws) return LFFT_E_ARG;
 
 int lwt_decompose(lwt_plan_t plan, const void* samples, const float* const* masks, void* coeffs,

@@ -119,4 +119,24 @@ struct SplitDesc {
   FastDiv fKN[4], fHM[4], fE;
 };
 
+// One level of the q-channel split, q = |det J| > 2 (natural orders).  The
+// fiber of k in G(N_l^T) is h_l = k + N_l^T g_l reduced into the Hermite box
+// of M_l^T, g_0 = 0, g_1 .. g_{q-1} the other classes of G(J^T) in the natural
+// order of the Hermite box of J^T.
+constexpr int kMaxQ = 16;
+
+struct SplitQDesc {
+  long long mM;               // |det M_l|
+  long long mN;               // |det N_l| = mM / q
+  int d;
+  int q;
+  int KN[4];                  // natural box of N_l^T (Hermite diagonal)
+  int HM[4][4];               // column Hermite form of M_l^T
+  long long hstride[4];
+  int s[kMaxQ][4];            // N_l^T g_l reduced into the M_l^T box (s[0] = 0)
+  float rsq;                  // 1 / sqrt(q)
+  int narrow;                 // 32-bit index path (bounds checked on the host)
+  FastDiv fKN[4], fHM[4];
+};
+
 }  // namespace lfft

@@ -54,4 +54,15 @@ hipError_t launch_unsplit_mask_grad(const SplitDesc& sd, long long batch, const 
                                     const float2* d2, long long d_bs, const float2* g,
                                     long long g_bs, float* gmask, hipStream_t s);
 
+// q-channel split of one level, q = |det J| > 2: ahat [B][m_l] (batch stride
+// ah_bs) -> channel 0 into d0 [B][m_l/q] (stride d0_bs) and channels
+// 1 .. q-1 into dw [B][q-1][m_l/q] (batch stride dw_bs, channel stride m_l/q).
+hipError_t launch_split_q(const SplitQDesc& sd, long long batch, const float2* ahat, long long ah_bs,
+                          const float* mask, float2* d0, long long d0_bs, float2* dw,
+                          long long dw_bs, hipStream_t s);
+// Its inverse (synthesis), same layouts.
+hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2* d0,
+                            long long d0_bs, const float2* dw, long long dw_bs, const float* mask,
+                            float2* ahat, long long ah_bs, hipStream_t s);
+
 }  // namespace lfft

@@ -729,6 +729,68 @@ void dilation_data(const Mat& J, Vec4& g0, Vec4& v) {
 }
 }  // namespace
 
+namespace {
+// 32-bit fiber maps: every intermediate of the reductions below 2^30 in
+// magnitude.  The reduction starts from k (< KN) or h0 + s (< 2 HM_ii per
+// coordinate); reducing coordinate i subtracts q_i * column i with
+// |q_i| <= bound_i / HM_ii + 1 from the coordinates above it.
+bool fiber_maps_fit_32(const Mat& HN, const Mat& HMt, i64 ml) {
+  const int d = HN.d;
+  const i64 lim = i64(1) << 30;
+  std::vector<i64> bnd(d);
+  for (int i = 0; i < d; ++i) bnd[i] = std::max<i64>(HN.a[i][i], 2 * HMt.a[i][i]);
+  bool ok = ml < (i64(1) << 28);
+  for (int i = d - 1; i >= 0 && ok; --i) {
+    const i64 t = bnd[i] / HMt.a[i][i] + 1;
+    for (int r = 0; r < i; ++r) {
+      bnd[r] += t * HMt.a[r][i];
+      if (bnd[r] >= lim) ok = false;
+    }
+    bnd[i] = HMt.a[i][i];
+  }
+  return ok;
+}
+
+// q-channel split descriptor of one level (q > 2): the natural boxes of
+// N_l^T and M_l^T and the fiber offsets s_l = N_l^T g_l.
+void fill_split_q(WaveLevel& L, const std::vector<Vec4>& gcls, int q) {
+  SplitQDesc& sq = L.sq;
+  const int d = L.Ml.d;
+  sq.mM = L.ml;
+  sq.mN = L.ml / q;
+  sq.d = d;
+  sq.q = q;
+  Mat HN, UN, HMt, UMt;
+  hnf(transpose(L.Nl), HN, UN);
+  hnf(transpose(L.Ml), HMt, UMt);
+  i64 st = 1;
+  for (int i = d - 1; i >= 0; --i) {
+    sq.hstride[i] = st;
+    st *= HMt.a[i][i];
+  }
+  for (int i = 0; i < 4; ++i) {
+    sq.KN[i] = i < d ? (int)HN.a[i][i] : 1;
+    if (i >= d) sq.hstride[i] = 0;
+    for (int j = 0; j < 4; ++j) sq.HM[i][j] = (i < d && j < d) ? (int)HMt.a[i][j] : 0;
+  }
+  for (int l = 0; l < kMaxQ; ++l)
+    for (int i = 0; i < 4; ++i) sq.s[l][i] = 0;
+  for (int l = 0; l < q; ++l) {
+    Vec4 s = zero4();
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) s[i] = cadd(s[i], cmul(L.Nl.a[j][i], gcls[l][j]));
+    s = reduce4(HMt, s);
+    for (int i = 0; i < 4; ++i) sq.s[l][i] = (int)s[i];
+  }
+  sq.rsq = (float)(1.0 / std::sqrt((double)q));
+  sq.narrow = fiber_maps_fit_32(HN, HMt, L.ml) ? 1 : 0;
+  for (int i = 0; i < 4; ++i) {
+    sq.fKN[i] = make_fast_div(i < d ? HN.a[i][i] : 1);
+    sq.fHM[i] = make_fast_div(i < d ? HMt.a[i][i] : 1);
+  }
+}
+}  // namespace
+
 WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64 batch,
                           uint32_t flags) {
   if (d < 1 || d > kMaxD || !Mrm || !Jrm || levels < 1 || batch < 1) throw StatusError{E_ARG};
@@ -740,13 +802,31 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
     w->levels = levels;
     w->batch = batch;
     i64 DJ = det(w->J);
-    if (DJ != 2 && DJ != -2) throw StatusError{E_UNSUPPORTED};
+    if (DJ == 0) throw StatusError{E_SINGULAR};
+    const i64 q = DJ < 0 ? -DJ : DJ;
+    if (q < 2 || q > kMaxQ) throw StatusError{E_UNSUPPORTED};
+    w->q = (int)q;
     i64 DM = det(w->M);
     if (DM == 0) throw StatusError{E_SINGULAR};
     w->m = DM < 0 ? -DM : DM;
     w->fftM = build_lattice_plan(d, Mrm, batch, flags);
-    Vec4 g0, v;
-    dilation_data(w->J, g0, v);
+    Vec4 g0 = zero4(), v = zero4();
+    if (q == 2) dilation_data(w->J, g0, v);
+    // q > 2: the classes of G(J^T), natural order of the Hermite box of J^T
+    std::vector<Vec4> gcls;
+    if (q > 2) {
+      Mat HJ, UJ;
+      hnf(transpose(w->J), HJ, UJ);
+      for (i64 idx = 0; idx < q; ++idx) {
+        Vec4 g = zero4();
+        i64 r = idx;
+        for (int i = d - 1; i >= 0; --i) {
+          g[i] = r % HJ.a[i][i];
+          r /= HJ.a[i][i];
+        }
+        gcls.push_back(g);
+      }
+    }
     TwCache tw{&w->blob, {}, {}};
     Mat Ml = w->M;
     for (int l = 0; l < levels; ++l) {
@@ -759,11 +839,18 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
       }
       i64 dm = det(Ml);
       L.ml = dm < 0 ? -dm : dm;
-      if (L.ml % 2 != 0) throw StatusError{E_NOT_INTEGRAL};
+      if (L.ml % q != 0) throw StatusError{E_NOT_INTEGRAL};
       i64 nrm[16];
       for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) nrm[i * d + j] = L.Nl.a[i][j];
       L.fftN = build_lattice_plan(d, nrm, batch, flags);
+      if (q > 2) {
+        L.fftW = build_lattice_plan(d, nrm, q - 1, flags);
+        fill_split_q(L, gcls, (int)q);
+        w->lv.push_back(L);
+        Ml = L.Nl;
+        continue;
+      }
       // split descriptor
       SplitDesc& sd = L.sd;
       sd.mM = L.ml;
@@ -816,18 +903,7 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
       // reducing coordinate i subtracts q_i * column i with
       // |q_i| <= bound_i / HM_ii + 1 from the coordinates above it.
       {
-        const i64 lim = i64(1) << 30;
-        std::vector<i64> bnd(d);
-        for (int i = 0; i < d; ++i) bnd[i] = std::max<i64>(HN.a[i][i], 2 * HMt.a[i][i]);
-        bool ok = L.ml < (i64(1) << 28);
-        for (int i = d - 1; i >= 0 && ok; --i) {
-          const i64 q = bnd[i] / HMt.a[i][i] + 1;
-          for (int r = 0; r < i; ++r) {
-            bnd[r] += q * HMt.a[r][i];
-            if (bnd[r] >= lim) ok = false;
-          }
-          bnd[i] = HMt.a[i][i];
-        }
+        bool ok = fiber_maps_fit_32(HN, HMt, L.ml);
         i64 hsum = 0;
         for (int i = 0; i < d; ++i) hsum += HMt.a[i][i];
         if (hsum * E >= (i64(1) << 31)) ok = false;
@@ -842,10 +918,14 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
       Ml = L.Nl;
     }
     size_t fws = w->fftM->ws_elems;
-    for (auto& L : w->lv) fws = std::max(fws, L.fftN->ws_elems);
-    // small levels: batch * m_l / 2 at most kChannelBatchElems points
+    for (auto& L : w->lv) {
+      fws = std::max(fws, L.fftN->ws_elems);
+      if (L.fftW) fws = std::max(fws, L.fftW->ws_elems);
+    }
+    // small levels: batch * m_l / 2 at most kChannelBatchElems points (q = 2;
+    // the q > 2 pyramid runs its levels in order on one stream)
     w->small_from = levels;
-    while (w->small_from > 0 &&
+    while (q == 2 && w->small_from > 0 &&
            batch * (w->lv[w->small_from - 1].ml / 2) <= kChannelBatchElems)
       --w->small_from;
     size_t chan_ws = 0;
@@ -865,7 +945,7 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
     w->big_d2.assign(levels, 0);
     w->bd_elems = 0;
     size_t fws2 = 0;
-    for (int l = 0; l < w->small_from; ++l) {
+    for (int l = 0; l < (q == 2 ? w->small_from : 0); ++l) {
       w->big_d2[l] = (i64)w->bd_elems;
       w->bd_elems += (size_t)(batch * (w->lv[l].ml / 2));
       fws2 = std::max(fws2, w->lv[l].fftN->ws_elems);
@@ -930,7 +1010,10 @@ void build_channel_batches(WavePlan* w) {
 
 void upload_wave_plan(WavePlan* w) {
   upload_plan(w->fftM);
-  for (auto& L : w->lv) upload_plan(L.fftN);
+  for (auto& L : w->lv) {
+    upload_plan(L.fftN);
+    if (L.fftW) upload_plan(L.fftW);
+  }
   if (!w->chan_dec) build_channel_batches(w);
   if (!w->s2) {
     if (hipStreamCreateWithFlags(&w->s2, hipStreamNonBlocking) != hipSuccess) {
@@ -943,11 +1026,12 @@ void upload_wave_plan(WavePlan* w) {
     if (hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming) != hipSuccess)
       throw StatusError{E_HIP};
   }
-  if (!w->dtab) {
+  if (!w->dtab && !w->blob.bytes.empty()) {
     w->dtab = upload_blob(w->blob);
     uintptr_t base = reinterpret_cast<uintptr_t>(w->dtab);
     for (auto& L : w->lv) patch(L.sd.tw, base);
   }
+  w->uploaded = true;
 }
 
 void free_wave_plan(WavePlan* w) {
@@ -959,7 +1043,10 @@ void free_wave_plan(WavePlan* w) {
   free_batch_plan(w->chan_dec);
   free_batch_plan(w->chan_rec);
   free_plan(w->fftM);
-  for (auto& L : w->lv) free_plan(L.fftN);
+  for (auto& L : w->lv) {
+    free_plan(L.fftN);
+    free_plan(L.fftW);
+  }
   if (w->dtab) (void)hipFree(w->dtab);
   delete w;
 }
@@ -1014,10 +1101,16 @@ void dirichlet_mask(const WavePlan* w, int level, float* out) {
       if (tw2 > n) inside = false;
       if (tw2 == n) ++rN;
     }
+    // sqrt(q) 2^{(rM - rN)/2}, q = m / n (the quotient of the Dirichlet
+    // kernels' coefficients); 2^{(1 + rM - rN)/2} for q = 2
     double val = 0.0;
     if (inside) {
-      int e = 1 + rM - rN;
-      val = (e % 2 == 0) ? std::ldexp(1.0, e / 2) : std::ldexp(std::sqrt(2.0), (e - 1) / 2);
+      const i64 q = m / n;
+      const int e = rM - rN;
+      const double p2 = (e % 2 == 0) ? std::ldexp(1.0, e / 2) : std::ldexp(std::sqrt(2.0), (e - 1) / 2);
+      val = q == 2 ? ((e + 1) % 2 == 0 ? std::ldexp(1.0, (e + 1) / 2)
+                                       : std::ldexp(std::sqrt(2.0), e / 2))
+                   : std::sqrt((double)q) * p2;
     }
     out[idx] = (float)val;
   }

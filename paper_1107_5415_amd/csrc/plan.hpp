@@ -112,7 +112,9 @@ struct WaveLevel {
   Mat Ml, Nl;
   i64 ml = 0;
   LatticePlan* fftN = nullptr;
-  SplitDesc sd{};
+  SplitDesc sd{};           // q = 2
+  SplitQDesc sq{};          // q > 2
+  LatticePlan* fftW = nullptr;  // q > 2: the q - 1 wavelet channels (batch q - 1)
 };
 
 struct BatchPlan;
@@ -120,13 +122,15 @@ struct BatchPlan;
 struct WavePlan {
   int d = 0;
   Mat M, J;
+  int q = 2;                // |det J|: channels per level
   int levels = 0;
   i64 batch = 1;
   i64 m = 0;
   LatticePlan* fftM = nullptr;
   std::vector<WaveLevel> lv;
   Blob blob;
-  void* dtab = nullptr;
+  void* dtab = nullptr;     // device copy of blob (empty for q > 2)
+  bool uploaded = false;    // every device table of the pyramid is resident
   size_t ws_elems = 0;
   // Channel FFTs of the small levels (small_from .. levels-1, and the final
   // low-pass channel) run as one batched launch: the splits leave their

@@ -1,6 +1,7 @@
 // Multi-level wavelet pyramid on the device (Section 5.3: one lattice FFT,
 // then steps 3-4 on the low-pass Fourier data of every level, and one
-// inverse FFT per channel), its inverse and both adjoints.
+// inverse FFT per channel), its inverse and both adjoints (|det J| = 2), and
+// the q-channel pyramid for |det J| = q > 2 (no adjoints).
 //
 // Layouts (complex64, batch outermost):
 //   samples  : [B][m]  natural order of G(M)
@@ -75,13 +76,103 @@ long long coeff_offset(const WavePlan* w, int level) {
 }  // namespace
 
 size_t wave_saved_elems(const WavePlan* w) {
+  if (w->q != 2) return 0;
   size_t s = 0;
   for (auto& L : w->lv) s += (size_t)(w->batch * L.ml);
   return s;
 }
 
+// ---------------------------------------------------------------------------
+// q = |det J| > 2: coefficients [B][m] = [lvl 1: ch 1 | .. | ch q-1] ..
+// [lvl L: ch 1 | .. | ch q-1] [ch 0 of lvl L], each block in natural sample
+// order of N_l.  Workspace: F0 (B m), F1 (B m / q), D (B (q-1) m / q), FW.
+// The levels run in order on the caller's stream.
+namespace {
+struct QBufs {
+  float2* F0;
+  float2* F1;
+  float2* D;
+  float2* FW;
+};
+
+QBufs carve_q(const WavePlan* w, void* ws) {
+  float2* base = static_cast<float2*>(ws);
+  const long long bm = w->batch * w->m;
+  QBufs b;
+  b.F0 = base;
+  b.F1 = base + bm;
+  b.D = b.F1 + bm / w->q;
+  b.FW = base + 2 * bm;
+  return b;
+}
+
+long long coeff_offset_q(const WavePlan* w, int level) {
+  long long off = 0;
+  for (int l = 0; l < level; ++l) off += (w->q - 1) * (w->lv[l].ml / w->q);
+  return off;
+}
+
+// algorithmic bytes of one q-channel split/unsplit level
+double split_q_bytes(long long B, long long ml) { return (16.0 * (double)B + 4.0) * (double)ml; }
+
+// buffer written by level l of the synthesis walk (l = L-1 .. 0)
+float2* q_target(const QBufs& b, int l) { return l % 2 == 0 ? b.F0 : b.F1; }
+
+void decompose_q(const WavePlan* w, const float2* x, const float* const* masks, float2* coeffs,
+                 void* ws, hipStream_t s) {
+  QBufs b = carve_q(w, ws);
+  const long long B = w->batch, m = w->m, q = w->q;
+  exec_lattice(w->fftM, false, false, false, x, b.F0, b.FW, m, m, s);
+  float2* cur = b.F0;
+  for (int l = 0; l < w->levels; ++l) {
+    const WaveLevel& V = w->lv[l];
+    const long long n = V.ml / q;
+    float2* next = cur == b.F0 ? b.F1 : b.F0;
+    {
+      TraceScope ts("split_q_kernel", split_q_bytes(B, V.ml), s);
+      check(launch_split_q(V.sq, B, cur, V.ml, masks[l], next, n, b.D, (q - 1) * n, s));
+    }
+    const long long off = coeff_offset_q(w, l);
+    for (long long i = 0; i < B; ++i)
+      exec_lattice(V.fftW, true, false, false, b.D + i * (q - 1) * n, coeffs + i * m + off, b.FW,
+                   n, n, s);
+    cur = next;
+  }
+  const WaveLevel& VL = w->lv[w->levels - 1];
+  exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset_q(w, w->levels), b.FW,
+               VL.ml / q, m, s);
+}
+
+void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* masks, float2* x,
+                   void* ws, hipStream_t s) {
+  QBufs b = carve_q(w, ws);
+  const long long B = w->batch, m = w->m, q = w->q;
+  const int L = w->levels;
+  const WaveLevel& VL = w->lv[L - 1];
+  exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset_q(w, L), q_target(b, L), b.FW,
+               m, VL.ml / q, s);
+  for (int l = L - 1; l >= 0; --l) {
+    const WaveLevel& V = w->lv[l];
+    const long long n = V.ml / q;
+    const long long off = coeff_offset_q(w, l);
+    for (long long i = 0; i < B; ++i)
+      exec_lattice(V.fftW, false, false, false, coeffs + i * m + off, b.D + i * (q - 1) * n, b.FW,
+                   n, n, s);
+    TraceScope ts("unsplit_q_kernel", split_q_bytes(B, V.ml), s);
+    check(launch_unsplit_q(V.sq, B, q_target(b, l + 1), n, b.D, (q - 1) * n, masks[l],
+                           q_target(b, l), V.ml, s));
+  }
+  exec_lattice(w->fftM, true, false, false, b.F0, x, b.FW, m, m, s);
+}
+}  // namespace
+
 void wave_decompose(const WavePlan* w, const float2* x, const float* const* masks, float2* coeffs,
                     float2* saved, void* ws, hipStream_t s) {
+  if (w->q != 2) {
+    if (saved) throw StatusError{E_UNSUPPORTED};
+    decompose_q(w, x, masks, coeffs, ws, s);
+    return;
+  }
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
@@ -134,6 +225,11 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
 
 void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* const* masks,
                       float2* x, float2* saved, void* ws, hipStream_t s) {
+  if (w->q != 2) {
+    if (saved) throw StatusError{E_UNSUPPORTED};
+    reconstruct_q(w, coeffs, masks, x, ws, s);
+    return;
+  }
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
@@ -209,6 +305,7 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
 void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* saved,
                              const float* const* masks, float2* gx, float* const* gmasks, void* ws,
                              hipStream_t s) {
+  if (w->q != 2) throw StatusError{E_UNSUPPORTED};
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
@@ -242,6 +339,7 @@ void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* 
 void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2* saved,
                                const float* const* masks, float2* gc, float* const* gmasks,
                                void* ws, hipStream_t s) {
+  if (w->q != 2) throw StatusError{E_UNSUPPORTED};
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;

@@ -10,6 +10,11 @@
 // The batch loop runs inside the thread, so the index arithmetic is paid once
 // per fiber and the mask gradient needs no atomics: each mask entry has
 // exactly one writer.
+//
+// For q = |det J| > 2 (split_q_kernel / unsplit_q_kernel) a thread owns the
+// q-point fiber {k + N^T g_l} and applies the orthogonal q x q channel matrix
+// built from the scaling mask (first row a / sqrt q, the other rows from a
+// Householder reflection).
 #include <hip/hip_runtime.h>
 
 #include "fft_common.hpp"
@@ -40,7 +45,8 @@ __device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
   return q;
 }
 
-__device__ __forceinline__ void reduce_hm(const SplitDesc& sd, long long* v) {
+template <class SD>
+__device__ __forceinline__ void reduce_hm(const SD& sd, long long* v) {
   for (int i = sd.d - 1; i >= 0; --i) {
     long long q = floordiv_ll(v[i], sd.HM[i][i]);
     if (q)
@@ -74,7 +80,8 @@ __device__ __forceinline__ Fiber fiber_of(const SplitDesc& sd, long long klin) {
 
 // 32-bit fiber maps (sd.narrow): the same arithmetic with invariant-divisor
 // multiplications instead of 64-bit divisions.
-__device__ __forceinline__ void reduce_hm32(const SplitDesc& sd, int* v) {
+template <class SD>
+__device__ __forceinline__ void reduce_hm32(const SD& sd, int* v) {
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
     if (i < sd.d) {
@@ -203,6 +210,182 @@ __global__ void unsplit_mask_grad_kernel(SplitDesc sd, long long batch, const fl
   gmask[f.i1] = s1 * kInvSqrt2;
 }
 
+// ---------------------------------------------------------------------------
+// q-channel split, q = |det J| > 2 (Section 5.3 step 4 for general |det J|).
+// Per fiber u_l = a(h_l) / sqrt q; the channel matrix has first row u and the
+// other rows from the reflection H = I - c v v^T, v = u + sigma e_0,
+// sigma = sign(u_0) (+1 at 0), c = 2 / (v^T v); v^T v >= 1, so c needs no
+// guard and the rows lose no accuracy near u = e_0:
+//   dhat_0 = sum_l u_l x_l,  t = dhat_0 + sigma x_0,
+//   dhat_j = x_j - c u_j t                                (j >= 1)
+// and the synthesis (its transpose), with tau = sum_{j>=1} u_j y_j:
+//   x_0 = u_0 y_0 - c v_0 tau,  x_l = u_l y_0 + y_l - c u_l tau   (l >= 1).
+// Q > 0 fixes q at compile time; Q = 0 reads it from the descriptor.
+template <int Q>
+__device__ __forceinline__ void fiber_q(const SplitQDesc& sd, long long klin, long long* idx) {
+  constexpr int QM = Q ? Q : kMaxQ;
+  const int q = Q ? Q : sd.q;
+  if (sd.narrow) {
+    int k[4] = {0, 0, 0, 0};
+    unsigned r = (unsigned)klin;
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      if (i < sd.d) {
+        const unsigned t = fast_div(r, sd.fKN[i]);
+        k[i] = (int)(r - t * (unsigned)sd.KN[i]);
+        r = t;
+      }
+    }
+    reduce_hm32(sd, k);
+#pragma unroll
+    for (int l = 0; l < QM; ++l) {
+      if (l < q) {
+        int h[4] = {k[0] + sd.s[l][0], k[1] + sd.s[l][1], k[2] + sd.s[l][2], k[3] + sd.s[l][3]};
+        if (l) reduce_hm32(sd, h);
+        int o = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < sd.d) o += h[i] * (int)sd.hstride[i];
+        idx[l] = o;
+      }
+    }
+  } else {
+    long long k[4] = {0, 0, 0, 0};
+    long long r = klin;
+    for (int i = sd.d - 1; i >= 0; --i) {
+      k[i] = r % sd.KN[i];
+      r /= sd.KN[i];
+    }
+    reduce_hm(sd, k);
+#pragma unroll
+    for (int l = 0; l < QM; ++l) {
+      if (l < q) {
+        long long h[4] = {k[0] + sd.s[l][0], k[1] + sd.s[l][1], k[2] + sd.s[l][2],
+                          k[3] + sd.s[l][3]};
+        if (l) reduce_hm(sd, h);
+        long long o = 0;
+        for (int i = 0; i < sd.d; ++i) o += h[i] * sd.hstride[i];
+        idx[l] = o;
+      }
+    }
+  }
+}
+
+// u_l, sigma, v_0 and c of one fiber
+template <int Q>
+__device__ __forceinline__ void reflector(const SplitQDesc& sd, const float* __restrict__ mask,
+                                          const long long* idx, float* u, float& sigma,
+                                          float& v0, float& c) {
+  constexpr int QM = Q ? Q : kMaxQ;
+  const int q = Q ? Q : sd.q;
+  float perp = 0.f;
+#pragma unroll
+  for (int l = 0; l < QM; ++l) {
+    if (l < q) {
+      u[l] = mask[idx[l]] * sd.rsq;
+      if (l) perp += u[l] * u[l];
+    }
+  }
+  sigma = u[0] >= 0.f ? 1.f : -1.f;
+  v0 = u[0] + sigma;
+  c = 2.f / (v0 * v0 + perp);
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256) split_q_kernel(SplitQDesc sd, long long batch,
+                                                      const float2* __restrict__ ah, long long ah_bs,
+                                                      const float* __restrict__ mask,
+                                                      float2* __restrict__ d0, long long d0_bs,
+                                                      float2* __restrict__ dw, long long dw_bs) {
+  constexpr int QM = Q ? Q : kMaxQ;
+  const int q = Q ? Q : sd.q;
+  const long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= sd.mN) return;
+  long long idx[QM];
+  fiber_q<Q>(sd, k, idx);
+  float u[QM], sigma, v0, c;
+  reflector<Q>(sd, mask, idx, u, sigma, v0, c);
+  for (long long b = 0; b < batch; ++b) {
+    float2 x[QM];
+#pragma unroll
+    for (int l = 0; l < QM; ++l)
+      if (l < q) x[l] = ah[b * ah_bs + idx[l]];
+    float2 y0 = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l < QM; ++l)
+      if (l < q) y0 = axpby(1.f, y0, u[l], x[l]);
+    const float2 t = axpby(1.f, y0, sigma, x[0]);
+    d0[b * d0_bs + k] = y0;
+    float2* o = dw + b * dw_bs + k;
+#pragma unroll
+    for (int j = 1; j < QM; ++j)
+      if (j < q) o[(j - 1) * sd.mN] = axpby(1.f, x[j], -c * u[j], t);
+  }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256) unsplit_q_kernel(SplitQDesc sd, long long batch,
+                                                        const float2* __restrict__ d0,
+                                                        long long d0_bs,
+                                                        const float2* __restrict__ dw,
+                                                        long long dw_bs,
+                                                        const float* __restrict__ mask,
+                                                        float2* __restrict__ ah, long long ah_bs) {
+  constexpr int QM = Q ? Q : kMaxQ;
+  const int q = Q ? Q : sd.q;
+  const long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= sd.mN) return;
+  long long idx[QM];
+  fiber_q<Q>(sd, k, idx);
+  float u[QM], sigma, v0, c;
+  reflector<Q>(sd, mask, idx, u, sigma, v0, c);
+  for (long long b = 0; b < batch; ++b) {
+    float2 y[QM];
+    y[0] = d0[b * d0_bs + k];
+    const float2* in = dw + b * dw_bs + k;
+#pragma unroll
+    for (int j = 1; j < QM; ++j)
+      if (j < q) y[j] = in[(j - 1) * sd.mN];
+    float2 tau = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 1; j < QM; ++j)
+      if (j < q) tau = axpby(1.f, tau, u[j], y[j]);
+    float2* o = ah + b * ah_bs;
+    o[idx[0]] = axpby(u[0], y[0], -c * v0, tau);
+#pragma unroll
+    for (int l = 1; l < QM; ++l)
+      if (l < q) o[idx[l]] = axpby(1.f, axpby(u[l], y[0], 1.f, y[l]), -c * u[l], tau);
+  }
+}
+
+template <int Q>
+hipError_t launch_q(const SplitQDesc& sd, bool inverse, long long batch, const float2* a,
+                    long long a_bs, const float* mask, const float2* d0c, float2* d0,
+                    long long d0_bs, const float2* dwc, float2* dw, long long dw_bs, float2* ah,
+                    hipStream_t s) {
+  const unsigned grid = (unsigned)((sd.mN + 255) / 256);
+  if (inverse)
+    hipLaunchKernelGGL(unsplit_q_kernel<Q>, dim3(grid), dim3(256), 0, s, sd, batch, d0c, d0_bs,
+                       dwc, dw_bs, mask, ah, a_bs);
+  else
+    hipLaunchKernelGGL(split_q_kernel<Q>, dim3(grid), dim3(256), 0, s, sd, batch, a, a_bs, mask,
+                       d0, d0_bs, dw, dw_bs);
+  return hipGetLastError();
+}
+
+hipError_t dispatch_q(const SplitQDesc& sd, bool inverse, long long batch, const float2* a,
+                      long long a_bs, const float* mask, const float2* d0c, float2* d0,
+                      long long d0_bs, const float2* dwc, float2* dw, long long dw_bs, float2* ah,
+                      hipStream_t s) {
+  if (sd.q < 3 || sd.q > kMaxQ) return hipErrorInvalidValue;
+  switch (sd.q) {
+    case 3: return launch_q<3>(sd, inverse, batch, a, a_bs, mask, d0c, d0, d0_bs, dwc, dw, dw_bs, ah, s);
+    case 4: return launch_q<4>(sd, inverse, batch, a, a_bs, mask, d0c, d0, d0_bs, dwc, dw, dw_bs, ah, s);
+    case 8: return launch_q<8>(sd, inverse, batch, a, a_bs, mask, d0c, d0, d0_bs, dwc, dw, dw_bs, ah, s);
+    default: return launch_q<0>(sd, inverse, batch, a, a_bs, mask, d0c, d0, d0_bs, dwc, dw, dw_bs, ah, s);
+  }
+}
+
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -236,6 +419,20 @@ hipError_t launch_unsplit_mask_grad(const SplitDesc& sd, long long batch, const 
   hipLaunchKernelGGL(unsplit_mask_grad_kernel, dim3(blocks_for(sd.mN, 256)), dim3(256), 0, s, sd,
                      batch, d1, d2, d_bs, g, g_bs, gmask);
   return hipGetLastError();
+}
+
+hipError_t launch_split_q(const SplitQDesc& sd, long long batch, const float2* ahat, long long ah_bs,
+                          const float* mask, float2* d0, long long d0_bs, float2* dw,
+                          long long dw_bs, hipStream_t s) {
+  return dispatch_q(sd, false, batch, ahat, ah_bs, mask, nullptr, d0, d0_bs, nullptr, dw, dw_bs,
+                    nullptr, s);
+}
+
+hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2* d0,
+                            long long d0_bs, const float2* dw, long long dw_bs, const float* mask,
+                            float2* ahat, long long ah_bs, hipStream_t s) {
+  return dispatch_q(sd, true, batch, nullptr, ah_bs, mask, d0, nullptr, d0_bs, dw, nullptr, dw_bs,
+                    ahat, s);
 }
 
 }  // namespace lfft

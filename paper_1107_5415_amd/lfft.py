@@ -280,6 +280,22 @@ class WaveletPlan:
             self.level_m.append(ml.value)
             self.level_N.append(N)
         self.m = self.level_m[0]
+        # channels per level, q = |det J| (exact for the small J accepted)
+        self.q = int(round(abs(np.linalg.det(self.J.astype(np.float64)))))
+
+    def coeff_blocks(self):
+        """[(level, channel, offset, length)] of the coefficient blocks:
+        q = 2: [d2^(1) | .. | d2^(L) | d1^(L)] (channel 1 of every level,
+        then channel 0 of the last); q > 2: channels 1 .. q-1 of every
+        level, then channel 0 of the last level."""
+        out, off = [], 0
+        for l, ml in enumerate(self.level_m):
+            n = ml // self.q
+            for j in range(1, self.q):
+                out.append((l, j, off, n))
+                off += n
+        out.append((self.levels - 1, 0, off, self.level_m[-1] // self.q))
+        return out
 
     def __del__(self):
         h = getattr(self, "_h", None)

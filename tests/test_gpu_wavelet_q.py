@@ -1,0 +1,119 @@
+"""GPU parity of the q-channel pyramid (|det J| = q > 2, Section 5.3 step 4
+for general q) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import lattice as L, wavelet as W, wavelet_q as Q
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+J2 = ((2, 0), (0, 2))
+J21 = ((2, 1), (0, 2))
+J3 = ((3, 0), (0, 1))
+JR = ((0, -2), (2, 0))
+J2_3D = ((2, 0, 0), (0, 2, 0), (0, 0, 2))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+CASES = [
+    ("j2_3", ((16, 0), (0, 16)), J2, 3, 2),
+    ("j2_sheared", ((12, 4), (-4, 8)), J2, 1, 1),
+    ("j21", ((7, 6), (2, 8)), J21, 1, 3),
+    ("j3", ((18, 6), (-6, 12)), J3, 1, 2),
+    ("rot_2", ((0, -16), (16, 0)), JR, 2, 1),
+    ("d3_q8", ((8, 0, 0), (0, 8, 4), (0, 0, 8)), J2_3D, 2, 2),
+    ("d1_q4", ((256,),), ((4,),), 3, 1),
+    ("q5", ((25, 0), (0, 5)), ((5, 0), (0, 1)), 2, 1),
+    ("two_pass_levels", ((512, 128), (-128, 512)), J2, 3, 1),
+]
+
+
+@pytest.mark.parametrize("name,M,J,levels,batch", CASES, ids=[c[0] for c in CASES])
+def test_decompose_reconstruct(name, M, J, levels, batch):
+    from paper_1107_5415_amd import lfft
+    m = abs(L.det(L.as_matrix(M)))
+    print("case", name, flush=True)
+    x = workloads.complex_normal(41, (batch, m))
+    w = lfft.WaveletPlan(M, J, levels, batch=batch)
+    masks = w.dirichlet_masks("cuda")
+    c = w.decompose(_dev(x), masks).cpu().numpy()
+    ref = Q.decompose(x.astype(np.complex128), M, J, levels)
+    assert rel_l2(c, ref) < TOL
+    cz = workloads.complex_normal(42, (batch, m))
+    xr = w.reconstruct(_dev(cz), masks).cpu().numpy()
+    assert rel_l2(xr, Q.reconstruct(cz.astype(np.complex128), M, J, levels)) < TOL
+
+
+def _random_qmf_masks(seed, M, J, levels):
+    """Real masks with the QMF identity (random positive values normalised
+    per fiber), one per level."""
+    out = []
+    for i, (Ml, _) in enumerate(W.level_matrices(M, J, levels)):
+        _, idx, ml = Q.fiber_maps(Ml, J)
+        q = idx.shape[0]
+        r = np.random.default_rng(seed + i).random(idx.shape) + 0.05
+        r *= np.sqrt(q) / np.linalg.norm(r, axis=0)
+        mk = np.zeros(ml)
+        mk[idx] = r
+        out.append(mk.astype(np.float32))
+    return out
+
+
+@pytest.mark.parametrize("M,J,levels", [
+    (((32, 0), (0, 32)), J2, 2),
+    (((9, 3), (-2, 5)), J3, 1),
+    (((8, 0, 0), (0, 8, 4), (0, 0, 8)), J2_3D, 1),
+])
+def test_random_qmf_masks(M, J, levels):
+    """Masks whose fibers hold several non-zero values exercise every term
+    of the channel matrix (the Dirichlet masks are mostly one-hot)."""
+    from paper_1107_5415_amd import lfft
+    m = abs(L.det(L.as_matrix(M)))
+    masks = _random_qmf_masks(7, M, J, levels)
+    x = workloads.complex_normal(43, (2, m))
+    w = lfft.WaveletPlan(M, J, levels, batch=2)
+    dm = [_dev(mk) for mk in masks]
+    c = w.decompose(_dev(x), dm)
+    ref = Q.decompose(x.astype(np.complex128), M, J, levels, masks=[mk.astype(np.float64) for mk in masks])
+    assert rel_l2(c.cpu().numpy(), ref) < TOL
+    xr = w.reconstruct(c, dm).cpu().numpy()
+    assert rel_l2(xr, x) < 2e-5
+
+
+def test_full_size_two_dimensional_dyadic():
+    """M = 4096 I (m = 2^24), J = 2 I (four channels), six levels."""
+    from paper_1107_5415_amd import lfft
+    M = ((4096, 0), (0, 4096))
+    x = workloads.complex_normal(44, 1 << 24)
+    w = lfft.WaveletPlan(M, J2, 6)
+    masks = w.dirichlet_masks("cuda")
+    c = w.decompose(_dev(x), masks)
+    ref = Q.decompose(x.astype(np.complex128), M, J2, 6)
+    assert rel_l2(c.cpu().numpy(), ref) < TOL
+    del ref
+    xr = w.reconstruct(c, masks).cpu().numpy()
+    assert rel_l2(xr, x) < 2e-5
+
+
+def test_adjoints_are_rejected():
+    from paper_1107_5415_amd import lfft
+    w = lfft.WaveletPlan(((16, 0), (0, 16)), J2, 1)
+    masks = w.dirichlet_masks("cuda")
+    x = _dev(workloads.complex_normal(45, 256))
+    with pytest.raises(lfft.LfftError) as e:
+        w.decompose(x, masks, saved=torch.empty(256, dtype=torch.complex64, device="cuda"))
+    assert e.value.code == -5
+    with pytest.raises(lfft.LfftError) as e:
+        w.decompose_backward(x, None, masks)
+    assert e.value.code == -5

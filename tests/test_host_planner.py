@@ -9,6 +9,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+from oracle import wavelet_q as WQ
 from oracle import lattice as L, wavelet as W
 import workloads
 
@@ -165,6 +166,29 @@ def test_wavelet_levels_and_masks(M, J, levels):
         assert set(np.unique(got)) <= {0.0, 1.0, float(np.float32(np.sqrt(2.0)))}
 
 
+@pytest.mark.parametrize("M,J,levels", [
+    (((16, 0), (0, 16)), ((2, 0), (0, 2)), 3),
+    (((7, 6), (2, 8)), ((2, 1), (0, 2)), 1),
+    (((18, 6), (-6, 12)), ((3, 0), (0, 1)), 1),
+    (((0, -16), (16, 0)), ((0, -2), (2, 0)), 2),
+    (((8, 0, 0), (0, 8, 4), (0, 0, 8)), ((2, 0, 0), (0, 2, 0), (0, 0, 2)), 2),
+    (((64,),), ((4,),), 3),
+])
+def test_wavelet_q_levels_and_masks(M, J, levels):
+    """|det J| = q > 2: level chain, channel count, coefficient layout and
+    the Dirichlet mask of every level against the oracle."""
+    w = lfft.WaveletPlan(M, J, levels, host_only=True)
+    q = abs(L.det(L.as_matrix(J)))
+    assert w.q == q
+    assert w.saved_elems() == 0
+    for l, (Ml, Nl) in enumerate(W.level_matrices(M, J, levels)):
+        assert tuple(map(tuple, w.level_N[l].tolist())) == Nl
+        assert w.level_m[l] == abs(L.det(Ml))
+        ref = WQ.dirichlet_mask(Ml, Nl).astype(np.float32)
+        assert np.array_equal(w.dirichlet_mask(l), ref)
+    assert w.coeff_blocks() == WQ.coeff_layout(M, J, levels)
+
+
 def test_wavelet_masks_large_level_chain():
     M = workloads.CONFIGS["grad"]["M"]
     w = lfft.WaveletPlan(M, workloads.J_QUINCUNX, 4, host_only=True)
@@ -187,8 +211,9 @@ def test_error_codes():
     assert _err(lambda: lfft.LatticePlan([[4, 0], [0, 4]], batch=0, host_only=True)) == -1
     # J^{-1} M not integral: quincunx needs rows of equal parity
     assert _err(lambda: lfft.WaveletPlan([[3, 0], [0, 4]], workloads.J_QUINCUNX, 1, host_only=True)) == -3
-    # |det J| != 2
-    assert _err(lambda: lfft.WaveletPlan([[8, 0], [0, 8]], [[2, 0], [0, 2]], 1, host_only=True)) == -5
+    # |det J| outside 2 .. 16
+    assert _err(lambda: lfft.WaveletPlan([[25, 0], [0, 25]], [[5, 0], [0, 5]], 1, host_only=True)) == -5
+    assert _err(lambda: lfft.WaveletPlan([[8, 0], [0, 8]], [[1, 0], [0, 1]], 1, host_only=True)) == -5
     # integral first level, non-integral later level
     assert _err(lambda: lfft.WaveletPlan([[4, 0], [0, 2]], workloads.J_X, 3, host_only=True)) == -3
     # a large prime cycle cannot be split to fit on chip
