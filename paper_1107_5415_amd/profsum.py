@@ -1,10 +1,12 @@
 """Summaries of rocprofv3 CSV output for the committed profiles.
 
   python -m paper_1107_5415_amd.profsum stats STATS_CSV --cmd "..." --out FILE
-      per-kernel calls / total / average duration from --kernel-trace --stats
+      [--trace TRACE_CSV --tail-kernel NAME --tail-n N]
+      per-kernel calls / total / average duration from --kernel-trace --stats,
+      and the average of the last N dispatches of one kernel
   python -m paper_1107_5415_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
       --copy-kib KIB --alg-bytes B --sources F1,F2 --cmd-fetch "..." --cmd-write "..."
-      --out JSON
+      --out JSON [--alg-per-write R]
       HBM bytes per launch of NAME from FETCH_SIZE and WRITE_SIZE (KiB per
       dispatch), each scaled by what the same counter reads for the plain
       copy kernel of COPY-KIB KiB in the same run.
@@ -26,7 +28,7 @@ def _short(name):
         "(lfft::PassDesc, HIP_vector_type<float, 2u> const*, HIP_vector_type<float, 2u>*)", "")
 
 
-def stats(path, cmd, out):
+def stats(path, cmd, out, trace=None, tail_kernel=None, tail_n=0):
     rows = list(csv.DictReader(open(path)))
     lines = ["# rocprofv3 --kernel-trace --stats summary", "# command: " + cmd, "",
              "%-72s %7s %12s %11s %6s" % ("kernel", "calls", "total_us", "avg_us", "pct")]
@@ -34,6 +36,14 @@ def stats(path, cmd, out):
         lines.append("%-72s %7d %12.1f %11.2f %6.2f" % (
             _short(r["Name"])[:72], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
             float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    if trace and tail_kernel and tail_n:
+        # the last tail_n dispatches of one kernel (the benchmark's traced
+        # pass runs last), from the per-dispatch kernel trace
+        tr = [r for r in csv.DictReader(open(trace)) if tail_kernel in r["Kernel_Name"]]
+        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr[-tail_n:]]
+        lines += ["", "# last %d dispatches of %s (the traced pass): avg_us %.2f, min %.2f, max %.2f"
+                  % (len(d), tail_kernel, statistics.mean(d), min(d), max(d))]
     open(out, "w").write("\n".join(lines) + "\n")
 
 
@@ -45,7 +55,7 @@ def _per_dispatch(path, counter):
         key = (r["Kernel_Name"], r["Dispatch_Id"])
         vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
     per = {}
-    for (name, _), v in vals.items():
+    for (name, _), v in sorted(vals.items(), key=lambda kv: int(kv[0][1])):
         per.setdefault(name, []).append(v)
     return per
 
@@ -58,7 +68,8 @@ def digest(sources):
     return h.hexdigest()[:16]
 
 
-def traffic(fetch_csv, write_csv, kernel, copy_kib, alg_bytes, sources, cmd_f, cmd_w, out):
+def traffic(fetch_csv, write_csv, kernel, copy_kib, alg_bytes, sources, cmd_f, cmd_w, out,
+            alg_per_write=None):
     fe = _per_dispatch(fetch_csv, "FETCH_SIZE")
     wr = _per_dispatch(write_csv, "WRITE_SIZE")
 
@@ -88,16 +99,36 @@ def traffic(fetch_csv, write_csv, kernel, copy_kib, alg_bytes, sources, cmd_f, c
     cw = max(find(wr, COPY_KERNEL, exact=False))
     sf = copy_kib / cf
     sw = copy_kib / cw
-    # mean over the kernel's dispatches: the same launch mix as the
-    # benchmark's per-launch average
-    kf = statistics.mean(find(fe, kernel)) * sf * 1024
-    kw = statistics.mean(find(wr, kernel)) * sw * 1024
+    f_all = [x * sf * 1024 for x in find(fe, kernel)]
+    w_all = [x * sw * 1024 for x in find(wr, kernel)]
+    extra = {}
+    if alg_per_write is None:
+        # mean over the kernel's dispatches (the run's launch mix must be the
+        # benchmark's)
+        kf = statistics.mean(f_all)
+        kw = statistics.mean(w_all)
+    else:
+        # launches of several sizes: the two runs dispatch the same sequence,
+        # so dispatch i pairs across them; its algorithmic bytes are
+        # alg_per_write times its (exact, write-once) output bytes.  The
+        # measured / algorithmic ratio over every dispatch scales the
+        # benchmark's per-launch algorithmic bytes.
+        if len(f_all) != len(w_all):
+            raise SystemExit("dispatch counts differ: %d vs %d" % (len(f_all), len(w_all)))
+        alg = [alg_per_write * w for w in w_all]
+        rf = sum(f_all) / sum(alg)
+        rw = sum(w_all) / sum(alg)
+        kf = rf * alg_bytes
+        kw = rw * alg_bytes
+        extra = {"dispatches": len(f_all), "alg_per_write": alg_per_write,
+                 "traffic_over_alg": rf + rw}
     data = json.load(open(out)) if os.path.exists(out) else {}
     data[kernel] = {
         "bytes_per_launch": kf + kw,
         "fetch_bytes_per_launch": kf,
         "write_bytes_per_launch": kw,
         "alg_bytes_per_launch": alg_bytes,
+        **extra,
         "copy_scale": {"fetch": sf, "write": sw, "copy_kib": copy_kib},
         "sources": sources,
         "source_digest": digest(sources),
@@ -114,6 +145,9 @@ def main():
     s.add_argument("csv")
     s.add_argument("--cmd", required=True)
     s.add_argument("--out", required=True)
+    s.add_argument("--trace", default=None)
+    s.add_argument("--tail-kernel", default=None)
+    s.add_argument("--tail-n", type=int, default=0)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -124,12 +158,13 @@ def main():
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--alg-per-write", type=float, default=None)
     a = ap.parse_args()
     if a.what == "stats":
-        stats(a.csv, a.cmd, a.out)
+        stats(a.csv, a.cmd, a.out, a.trace, a.tail_kernel, a.tail_n)
     elif a.what == "traffic":
         traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_kib, a.alg_bytes, a.sources.split(","),
-                a.cmd_fetch, a.cmd_write, a.out)
+                a.cmd_fetch, a.cmd_write, a.out, a.alg_per_write)
     else:
         ap.print_help()
         sys.exit(2)
