@@ -200,6 +200,35 @@ def variant_grad(torch, lfft, reps):
             "backward_over_forward": round((tb - tf) / tf, 2)}
 
 
+def variant_q4(torch, lfft, reps):
+    """Four channels per level: the large M = [[4096, 2048], [0, 4096]]
+    (m = 2^24) with J = 2 I and 4 levels, decomposition + reconstruction,
+    beside the quincunx pyramid of the same M with 8 levels (the same final
+    resolution m_L = 2^16)."""
+    import workloads
+    cfg = workloads.CONFIGS["q4"]
+    big = workloads.CONFIGS["large"]
+    m = 1 << 24
+    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], m)).cuda()
+    res = {}
+    for name, J, levels, q in (("q4_J2I_4_levels", cfg["J"], cfg["levels"], 4),
+                               ("q2_quincunx_8_levels", big["J"], big["levels"], 2)):
+        plan = lfft.WaveletPlan(cfg["M"], J, levels)
+        masks = plan.dirichlet_masks(torch.device("cuda:0"))
+        c = torch.empty_like(x)
+        y = torch.empty_like(x)
+        td = _time_ms(lambda: plan.decompose(x, masks, out=c), reps, torch)
+        tr = _time_ms(lambda: plan.reconstruct(c, masks, out=y), reps, torch)
+        ms = [m // q ** l for l in range(levels)]
+        n = [ml // q for ml in ms]
+        f = 2 * (fft_flops(m) + sum((q - 1) * fft_flops(k) for k in n) + fft_flops(n[-1]))
+        res[name] = {"decompose_ms": round(td, 4), "reconstruct_ms": round(tr, 4),
+                     "gflops": round(f / ((td + tr) / 1e3) / 1e9, 1),
+                     "rel_l2_roundtrip": float(torch.linalg.norm(y - x) / torch.linalg.norm(x))}
+    return {"workload": "M=[[4096,2048],[0,4096]] m=2^24 complex64 seed %d, Dirichlet masks" % cfg["seed"],
+            **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,7 +376,8 @@ def main():
         log("bench: variants (split-BF16, batched, differentiation)")
         out["variants"] = {"split_bf16": variant_split_bf16(torch, lfft, max(5, args.steps // 2)),
                            "batched": variant_batched(torch, lfft, max(5, args.steps // 2)),
-                           "grad": variant_grad(torch, lfft, max(3, args.steps // 4))}
+                           "grad": variant_grad(torch, lfft, max(3, args.steps // 4)),
+                           "q4": variant_q4(torch, lfft, max(5, args.steps // 2))}
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host (one step)")
         out["cpu_baseline"] = cpu_baseline(cfg, m, levels)

@@ -91,15 +91,17 @@ def test_random_qmf_masks(M, J, levels):
     assert rel_l2(xr, x) < 2e-5
 
 
-def test_full_size_two_dimensional_dyadic():
-    """M = 4096 I (m = 2^24), J = 2 I (four channels), six levels."""
+def test_full_size_four_channels():
+    """M = [[4096, 2048], [0, 4096]] (m = 2^24), J = 2 I (four channels),
+    four levels: the benchmark's q = 4 workload."""
     from paper_1107_5415_amd import lfft
-    M = ((4096, 0), (0, 4096))
-    x = workloads.complex_normal(44, 1 << 24)
-    w = lfft.WaveletPlan(M, J2, 6)
+    cfg = workloads.CONFIGS["q4"]
+    M, J, levels = cfg["M"], cfg["J"], cfg["levels"]
+    x = workloads.complex_normal(cfg["seed"], 1 << 24)
+    w = lfft.WaveletPlan(M, J, levels)
     masks = w.dirichlet_masks("cuda")
     c = w.decompose(_dev(x), masks)
-    ref = Q.decompose(x.astype(np.complex128), M, J2, 6)
+    ref = Q.decompose(x.astype(np.complex128), M, J, levels)
     assert rel_l2(c.cpu().numpy(), ref) < TOL
     del ref
     xr = w.reconstruct(c, masks).cpu().numpy()

@@ -20,6 +20,8 @@ J_QUINCUNX = ((1, 1), (1, -1))
 J_X = ((2, 0), (0, 1))
 J_Y = ((1, 0), (0, 2))
 J_D = ((1, -1), (1, 1))
+# |det J| = 4: four channels per level
+J_2I = ((2, 0), (0, 2))
 
 CONFIGS = {
     # d = 2 plain method: m = 1088, one quincunx level
@@ -33,6 +35,9 @@ CONFIGS = {
     # differentiation: m = 2^20, batch 16, 4 quincunx levels
     "grad": dict(M=((1024, 256), (0, 1024)), J=J_QUINCUNX, levels=4, batch=16, seed=5,
                  target_seed=6),
+    # four channels per level: the large M with J = 2 I, 4 levels (the same
+    # final resolution m_L = 2^16 as 8 quincunx levels)
+    "q4": dict(M=((4096, 2048), (0, 4096)), J=J_2I, levels=4, batch=1, seed=7),
 }
 
 
