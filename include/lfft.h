@@ -54,8 +54,8 @@ extern "C" {
 #define LFFT_E_SINGULAR (-2)     /* det M = 0                                 */
 #define LFFT_E_NOT_INTEGRAL (-3) /* J^{-1} M not integral at some level       */
 #define LFFT_E_OVERFLOW (-4)     /* exact integer work would exceed int64     */
-#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, an
-                                    adjoint with |det J| > 2, or an
+#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, mask
+                                    gradients with |det J| > 2, or an
                                     elementary divisor with a prime factor
                                     that cannot be split to fit on chip      */
 #define LFFT_E_HIP (-6)          /* a HIP call or kernel launch failed        */
@@ -147,7 +147,8 @@ int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, u
  * u = (a(h_l) / sqrt q)_l and the other rows from the reflection
  * I - 2 v v^T / (v^T v), v = u + sign(u_0) e_0 (sign(0) = +1); it is
  * orthogonal when the mask satisfies sum_l a(h_l)^2 = q.  q > 2 supports
- * lwt_decompose / lwt_reconstruct with saved = NULL only.  Errors: ARG,
+ * lwt_decompose / lwt_reconstruct with saved = NULL, and the two adjoints
+ * without mask gradients (grad_masks = NULL).  Errors: ARG,
  * SINGULAR, NOT_INTEGRAL, OVERFLOW, UNSUPPORTED (q > 16, d > 4), NOMEM,
  * HIP. */
 int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J, int levels,
@@ -192,8 +193,9 @@ int lwt_reconstruct(lwt_plan_t plan, const void* coeffs, const float* const* mas
 
 /* Adjoint of lwt_decompose: grad_samples = D^H grad_coeffs, and, if
  * grad_masks (host array of device pointers) is non-NULL, d loss / d mask_l
- * summed over the batch, using `saved` from lwt_decompose.  q = 2 only
- * (UNSUPPORTED otherwise), as lwt_reconstruct_backward. */
+ * summed over the batch, using `saved` from lwt_decompose.  For q > 2 only
+ * the sample gradient (grad_masks = NULL, saved ignored; UNSUPPORTED
+ * otherwise), as in lwt_reconstruct_backward. */
 int lwt_decompose_backward(lwt_plan_t plan, const void* grad_coeffs, const void* saved,
                            const float* const* masks, void* grad_samples, float* const* grad_masks,
                            void* workspace, hipStream_t stream);

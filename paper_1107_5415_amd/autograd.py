@@ -45,9 +45,7 @@ class WaveletDecompose(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, plan, *masks):
-        if plan.q != 2:
-            raise RuntimeError("the adjoint pyramid is available for |det J| = 2 only")
-        saved = plan.new_saved(x.device)
+        saved = plan.new_saved(x.device) if plan.q == 2 else None
         c = plan.decompose(x.contiguous(), list(masks), saved=saved)
         ctx.plan = plan
         ctx.save_for_backward(saved, *masks)
@@ -68,9 +66,7 @@ class WaveletReconstruct(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, c, plan, *masks):
-        if plan.q != 2:
-            raise RuntimeError("the adjoint pyramid is available for |det J| = 2 only")
-        saved = plan.new_saved(c.device)
+        saved = plan.new_saved(c.device) if plan.q == 2 else None
         x = plan.reconstruct(c.contiguous(), list(masks), saved=saved)
         ctx.plan = plan
         ctx.save_for_backward(saved, *masks)

@@ -1,7 +1,8 @@
 // Multi-level wavelet pyramid on the device (Section 5.3: one lattice FFT,
 // then steps 3-4 on the low-pass Fourier data of every level, and one
 // inverse FFT per channel), its inverse and both adjoints (|det J| = 2), and
-// the q-channel pyramid for |det J| = q > 2 (no adjoints).
+// the q-channel pyramid for |det J| = q > 2 (adjoints without mask
+// gradients).
 //
 // Layouts (complex64, batch outermost):
 //   samples  : [B][m]  natural order of G(M)
@@ -305,7 +306,13 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
 void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* saved,
                              const float* const* masks, float2* gx, float* const* gmasks, void* ws,
                              hipStream_t s) {
-  if (w->q != 2) throw StatusError{E_UNSUPPORTED};
+  if (w->q != 2) {
+    // the q-channel split's matrix is real, so the unsplit with the same
+    // masks is its adjoint and the synthesis is the adjoint of the analysis
+    if (gmasks) throw StatusError{E_UNSUPPORTED};
+    reconstruct_q(w, gc, masks, gx, ws, s);
+    return;
+  }
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
@@ -339,7 +346,11 @@ void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* 
 void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2* saved,
                                const float* const* masks, float2* gc, float* const* gmasks,
                                void* ws, hipStream_t s) {
-  if (w->q != 2) throw StatusError{E_UNSUPPORTED};
+  if (w->q != 2) {
+    if (gmasks) throw StatusError{E_UNSUPPORTED};
+    decompose_q(w, gx, masks, gc, ws, s);
+    return;
+  }
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
