@@ -119,6 +119,18 @@ struct SplitDesc {
   FastDiv fKN[4], fHM[4], fE;
 };
 
+// Consecutive levels l .. l+K-1 of the q = 2 split run as one launch: a
+// thread owns one fiber of the coarsest level and the tree of 2^K - 1 fibers
+// below it, so the low-pass data between the levels stays in registers.
+constexpr int kMaxChain = 4;
+
+struct SplitChain {
+  SplitDesc sd[kMaxChain];          // levels l .. l+K-1 (every one on the 32-bit path)
+  const float* mask[kMaxChain];     // scaling masks, natural G(M_j^T)
+  float2* d2[kMaxChain];            // wavelet channel of every level, natural G(N_j^T)
+  long long d2_bs[kMaxChain];       // batch strides of d2
+};
+
 // One level of the q-channel split, q = |det J| > 2 (natural orders).  The
 // fiber of k in G(N_l^T) is h_l = k + N_l^T g_l reduced into the Hermite box
 // of M_l^T, g_0 = 0, g_1 .. g_{q-1} the other classes of G(J^T) in the natural

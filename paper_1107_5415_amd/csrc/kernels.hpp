@@ -54,6 +54,14 @@ hipError_t launch_unsplit_mask_grad(const SplitDesc& sd, long long batch, const 
                                     const float2* d2, long long d_bs, const float2* g,
                                     long long g_bs, float* gmask, hipStream_t s);
 
+// Levels l .. l+K-1 (2 <= K <= kMaxChain, every level narrow) of the q = 2
+// split in one launch: ahat [B][m_l] -> d2 of every level (c.d2) and the
+// low-pass d1 of level l+K-1 [B][m_{l+K-1}/2]; and the inverse.
+hipError_t launch_split_chain(int K, const SplitChain& c, long long batch, const float2* ahat,
+                              long long ah_bs, float2* d1, long long d1_bs, hipStream_t s);
+hipError_t launch_unsplit_chain(int K, const SplitChain& c, long long batch, const float2* d1,
+                                long long d1_bs, float2* ahat, long long ah_bs, hipStream_t s);
+
 // q-channel split of one level, q = |det J| > 2: ahat [B][m_l] (batch stride
 // ah_bs) -> channel 0 into d0 [B][m_l/q] (stride d0_bs) and channels
 // 1 .. q-1 into dw [B][q-1][m_l/q] (batch stride dw_bs, channel stride m_l/q).

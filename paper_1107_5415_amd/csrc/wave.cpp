@@ -74,6 +74,161 @@ long long coeff_offset(const WavePlan* w, int level) {
   for (int l = 0; l < level; ++l) off += w->lv[l].ml / 2;
   return off;
 }
+
+// Levels fused into one split/unsplit launch (at most kMaxChain).
+constexpr int kChainLevels = 2;
+
+// Fourier data of level l's wavelet channel in the workspace (no `saved`):
+// the batched staging area for small levels, the second stream's buffer for
+// large ones, D2 otherwise.
+float2* d2_slot(const WavePlan* w, const Bufs& b, int l) {
+  const bool batched = w->chan_dec != nullptr;
+  if (batched && l >= w->small_from) return b.ST + w->stage_lvl[l];
+  if (l < w->small_from) return b.BD + w->big_d2[l];
+  return b.D2;
+}
+
+// Consecutive runs of levels [l0, l0 + K): a run of K > 1 levels needs the
+// 32-bit fiber maps on every level and a private d2 slot for each.
+std::vector<std::pair<int, int>> level_runs(const WavePlan* w, const Bufs& b) {
+  std::vector<std::pair<int, int>> runs;
+  int l = 0;
+  while (l < w->levels) {
+    int k = 0;
+    while (l + k < w->levels && k < kChainLevels && w->lv[l + k].sd.narrow &&
+           d2_slot(w, b, l + k) != b.D2)
+      ++k;
+    if (k < 2) k = 1;
+    runs.push_back({l, k});
+    l += k;
+  }
+  return runs;
+}
+
+SplitChain make_chain(const WavePlan* w, const Bufs& b, const float* const* masks, int l0, int K) {
+  SplitChain c{};
+  for (int j = 0; j < K; ++j) {
+    c.sd[j] = w->lv[l0 + j].sd;
+    c.mask[j] = masks[l0 + j];
+    c.d2[j] = d2_slot(w, b, l0 + j);
+    c.d2_bs[j] = w->lv[l0 + j].ml / 2;
+  }
+  return c;
+}
+
+// algorithmic bytes of a run: the finest input, every level's mask and d2,
+// and the coarsest d1
+double chain_bytes(const WavePlan* w, int l0, int K) {
+  const double B = (double)w->batch;
+  double by = 8.0 * B * (double)w->lv[l0].ml;
+  for (int j = l0; j < l0 + K; ++j) by += (4.0 + 4.0 * B) * (double)w->lv[j].ml;
+  by += 4.0 * B * (double)w->lv[l0 + K - 1].ml;
+  return by;
+}
+
+const char* chain_name(bool inverse, int K) {
+  static const char* fwd[] = {"", "", "split_chain_kernel<2>", "split_chain_kernel<3>",
+                              "split_chain_kernel<4>"};
+  static const char* inv[] = {"", "", "unsplit_chain_kernel<2>", "unsplit_chain_kernel<3>",
+                              "unsplit_chain_kernel<4>"};
+  return inverse ? inv[K] : fwd[K];
+}
+
+// Decomposition without `saved`: runs of levels fused, the large channels'
+// inverse FFTs on the second stream after their run, the small ones batched.
+void decompose_runs(const WavePlan* w, const float2* x, const float* const* masks,
+                    float2* coeffs, void* ws, hipStream_t s) {
+  Bufs b = carve(w, ws);
+  const long long B = w->batch, m = w->m;
+  const int L = w->levels;
+  const bool batched = w->chan_dec != nullptr;
+  float2* cur = b.F0;
+  exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
+  bool forked = false;
+  const auto runs = level_runs(w, b);
+  for (const auto& r : runs) {
+    const int l0 = r.first, K = r.second, lt = l0 + K - 1;
+    const long long half_t = w->lv[lt].ml / 2;
+    float2* next = (batched && lt + 1 == L) ? b.ST + w->stage_d1 : (cur == b.F0 ? b.F1 : b.F0);
+    if (K == 1) {
+      TraceScope ts("split_kernel", split_bytes(B, w->lv[l0].ml), s);
+      check(launch_split(w->lv[l0].sd, B, cur, w->lv[l0].ml, masks[l0], next, d2_slot(w, b, l0),
+                         half_t, s));
+    } else {
+      SplitChain c = make_chain(w, b, masks, l0, K);
+      TraceScope ts(chain_name(false, K), chain_bytes(w, l0, K), s);
+      check(launch_split_chain(K, c, B, cur, w->lv[l0].ml, next, half_t, s));
+    }
+    for (int l = l0; l <= lt; ++l) {
+      if (l >= w->small_from) continue;
+      // large channel: its inverse FFT overlaps the next runs
+      if (l == l0) fork(w, w->ev[l], s);
+      forked = true;
+      exec_lattice(w->lv[l].fftN, true, false, false, b.BD + w->big_d2[l],
+                   coeffs + coeff_offset(w, l), b.FW2, w->lv[l].ml / 2, m, w->s2);
+    }
+    cur = next;
+  }
+  if (batched) {
+    exec_batch(w->chan_dec, true, BATCH_PERSISTENT, b.ST, coeffs, b.FW, s);
+  } else {
+    const WaveLevel& VL = w->lv[L - 1];
+    exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset(w, L), b.FW, VL.ml / 2, m,
+                 s);
+  }
+  if (forked) join(w, s);
+}
+
+// Reconstruction without `saved`, runs of levels fused (the inverse walk).
+void reconstruct_runs(const WavePlan* w, const float2* coeffs, const float* const* masks,
+                      float2* x, void* ws, hipStream_t s) {
+  Bufs b = carve(w, ws);
+  const long long B = w->batch, m = w->m;
+  const int L = w->levels;
+  const bool batched = w->chan_rec != nullptr;
+  const auto runs = level_runs(w, b);
+  const int nr = (int)runs.size();
+  // run i (0 = finest) writes F0 or F1 alternately upwards from the finest
+  // run, which writes F0 for the final inverse FFT (F1 holds B m / 2, enough
+  // for every run above level 0)
+  auto out_of = [&](int i) { return (i % 2 == 0) ? b.F0 : b.F1; };
+  const WaveLevel& VL = w->lv[L - 1];
+  float2* cur = batched ? b.ST + w->stage_d1 : (out_of(nr - 1) == b.F0 ? b.F1 : b.F0);
+  const bool ahead = w->small_from > 0;
+  if (ahead) {
+    fork(w, w->ev_join, s);
+    for (int l = w->small_from - 1; l >= 0; --l) {
+      const WaveLevel& V = w->lv[l];
+      exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), b.BD + w->big_d2[l],
+                   b.FW2, m, V.ml / 2, w->s2);
+      check(hipEventRecord(w->ev[l], w->s2));
+    }
+  }
+  if (batched)
+    exec_batch(w->chan_rec, false, BATCH_PERSISTENT, coeffs, b.ST, b.FW, s);
+  else
+    exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset(w, L), cur, b.FW, m,
+                 VL.ml / 2, s);
+  for (int i = nr - 1; i >= 0; --i) {
+    const int l0 = runs[i].first, K = runs[i].second, lt = l0 + K - 1;
+    // large channels come from the second stream (without the batched
+    // launch every level is large)
+    for (int l = l0; l <= lt; ++l)
+      if (l < w->small_from) check(hipStreamWaitEvent(s, w->ev[l], 0));
+    float2* next = out_of(i);
+    if (K == 1) {
+      TraceScope ts("unsplit_kernel", split_bytes(B, w->lv[l0].ml), s);
+      check(launch_unsplit(w->lv[l0].sd, B, cur, d2_slot(w, b, l0), w->lv[l0].ml / 2, masks[l0],
+                           next, w->lv[l0].ml, s));
+    } else {
+      SplitChain c = make_chain(w, b, masks, l0, K);
+      TraceScope ts(chain_name(true, K), chain_bytes(w, l0, K), s);
+      check(launch_unsplit_chain(K, c, B, cur, w->lv[lt].ml / 2, next, w->lv[l0].ml, s));
+    }
+    cur = next;
+  }
+  exec_lattice(w->fftM, true, false, false, cur, x, b.FW, w->lv[0].ml, m, s);
+}
 }  // namespace
 
 size_t wave_saved_elems(const WavePlan* w) {
@@ -174,6 +329,10 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
     decompose_q(w, x, masks, coeffs, ws, s);
     return;
   }
+  if (!saved) {
+    decompose_runs(w, x, masks, coeffs, ws, s);
+    return;
+  }
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
@@ -229,6 +388,10 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
   if (w->q != 2) {
     if (saved) throw StatusError{E_UNSUPPORTED};
     reconstruct_q(w, coeffs, masks, x, ws, s);
+    return;
+  }
+  if (!saved) {
+    reconstruct_runs(w, coeffs, masks, x, ws, s);
     return;
   }
   Bufs b = carve(w, ws);

@@ -211,6 +211,119 @@ __global__ void unsplit_mask_grad_kernel(SplitDesc sd, long long batch, const fl
 }
 
 // ---------------------------------------------------------------------------
+// K consecutive levels of the q = 2 split in one launch.  The fibers form a
+// binary tree in heap order: node 0 is the fiber of the coarsest level at
+// k = t, and the children of node n (2n+1 and 2n+2) are the fibers of the
+// next finer level whose outputs k are node n's inputs i0 and i1 (G(M_{j+1}^T)
+// and G(N_j^T) are the same group in the same natural order).  Every node
+// does exactly the arithmetic of split_kernel / unsplit_kernel, so the chain
+// gives the same bits as K single-level launches.
+__host__ __device__ constexpr int node_depth(int n) {
+  return n == 0 ? 0 : 1 + node_depth((n - 1) / 2);
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) split_chain_kernel(SplitChain c, long long batch,
+                                                          const float2* __restrict__ ah,
+                                                          long long ah_bs, float2* __restrict__ d1,
+                                                          long long d1_bs) {
+  constexpr int NF = (1 << K) - 1;
+  constexpr int LEAF0 = (1 << (K - 1)) - 1;   // first node of the finest level
+  const long long t = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= c.sd[K - 1].mN) return;
+  int kk[NF], i0[NF], i1[NF];
+  float2 cphi[NF];
+  float a0[NF], a1[NF];
+  kk[0] = (int)t;
+#pragma unroll
+  for (int n = 0; n < NF; ++n) {
+    const int j = K - 1 - node_depth(n);
+    const Fiber f = fiber_of32(c.sd[j], kk[n]);
+    i0[n] = (int)f.i0;
+    i1[n] = (int)f.i1;
+    cphi[n] = cconj(f.phi);
+    if (n < LEAF0) {
+      kk[2 * n + 1] = i0[n];
+      kk[2 * n + 2] = i1[n];
+    }
+    a0[n] = c.mask[j][i0[n]] * kInvSqrt2;
+    a1[n] = c.mask[j][i1[n]] * kInvSqrt2;
+  }
+  for (long long b = 0; b < batch; ++b) {
+    float2 x0[NF - LEAF0], x1[NF - LEAF0];
+#pragma unroll
+    for (int n = LEAF0; n < NF; ++n) {
+      x0[n - LEAF0] = ah[b * ah_bs + i0[n]];
+      x1[n - LEAF0] = ah[b * ah_bs + i1[n]];
+    }
+    float2 lo[NF];
+#pragma unroll
+    for (int n = NF - 1; n >= 0; --n) {
+      const int j = K - 1 - node_depth(n);
+      const float2 u = n >= LEAF0 ? x0[n - LEAF0] : lo[2 * n + 1];
+      const float2 v = n >= LEAF0 ? x1[n - LEAF0] : lo[2 * n + 2];
+      lo[n] = axpby(a0[n], u, a1[n], v);
+      c.d2[j][b * c.d2_bs[j] + kk[n]] = cmul(cphi[n], axpby(a1[n], u, -a0[n], v));
+    }
+    d1[b * d1_bs + t] = lo[0];
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) unsplit_chain_kernel(SplitChain c, long long batch,
+                                                            const float2* __restrict__ d1,
+                                                            long long d1_bs,
+                                                            float2* __restrict__ ah,
+                                                            long long ah_bs) {
+  constexpr int NF = (1 << K) - 1;
+  constexpr int LEAF0 = (1 << (K - 1)) - 1;
+  const long long t = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= c.sd[K - 1].mN) return;
+  int kk[NF], i0[NF], i1[NF];
+  float2 phi[NF];
+  float a0[NF], a1[NF];
+  kk[0] = (int)t;
+#pragma unroll
+  for (int n = 0; n < NF; ++n) {
+    const int j = K - 1 - node_depth(n);
+    const Fiber f = fiber_of32(c.sd[j], kk[n]);
+    i0[n] = (int)f.i0;
+    i1[n] = (int)f.i1;
+    phi[n] = f.phi;
+    if (n < LEAF0) {
+      kk[2 * n + 1] = i0[n];
+      kk[2 * n + 2] = i1[n];
+    }
+    a0[n] = c.mask[j][i0[n]] * kInvSqrt2;
+    a1[n] = c.mask[j][i1[n]] * kInvSqrt2;
+  }
+  for (long long b = 0; b < batch; ++b) {
+    float2 y2[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) {
+      const int j = K - 1 - node_depth(n);
+      y2[n] = c.d2[j][b * c.d2_bs[j] + kk[n]];
+    }
+    float2 lo[NF];
+    lo[0] = d1[b * d1_bs + t];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) {
+      const float2 y1 = lo[n];
+      const float2 w = cmul(phi[n], y2[n]);
+      const float2 o0 = axpby(a0[n], y1, a1[n], w);
+      const float2 o1 = axpby(a1[n], y1, -a0[n], w);
+      if (n < LEAF0) {
+        lo[2 * n + 1] = o0;
+        lo[2 * n + 2] = o1;
+      } else {
+        ah[b * ah_bs + i0[n]] = o0;
+        ah[b * ah_bs + i1[n]] = o1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // q-channel split, q = |det J| > 2 (Section 5.3 step 4 for general |det J|).
 // Per fiber u_l = a(h_l) / sqrt q; the channel matrix has first row u and the
 // other rows from the reflection H = I - c v v^T, v = u + sigma e_0,
@@ -433,6 +546,30 @@ hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2*
                             float2* ahat, long long ah_bs, hipStream_t s) {
   return dispatch_q(sd, true, batch, nullptr, ah_bs, mask, d0, nullptr, d0_bs, dw, nullptr, dw_bs,
                     ahat, s);
+}
+
+hipError_t launch_split_chain(int K, const SplitChain& c, long long batch, const float2* ahat,
+                              long long ah_bs, float2* d1, long long d1_bs, hipStream_t s) {
+  const unsigned grid = blocks_for(c.sd[K - 1].mN, 256);
+  switch (K) {
+    case 2: hipLaunchKernelGGL(split_chain_kernel<2>, dim3(grid), dim3(256), 0, s, c, batch, ahat, ah_bs, d1, d1_bs); break;
+    case 3: hipLaunchKernelGGL(split_chain_kernel<3>, dim3(grid), dim3(256), 0, s, c, batch, ahat, ah_bs, d1, d1_bs); break;
+    case 4: hipLaunchKernelGGL(split_chain_kernel<4>, dim3(grid), dim3(256), 0, s, c, batch, ahat, ah_bs, d1, d1_bs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unsplit_chain(int K, const SplitChain& c, long long batch, const float2* d1,
+                                long long d1_bs, float2* ahat, long long ah_bs, hipStream_t s) {
+  const unsigned grid = blocks_for(c.sd[K - 1].mN, 256);
+  switch (K) {
+    case 2: hipLaunchKernelGGL(unsplit_chain_kernel<2>, dim3(grid), dim3(256), 0, s, c, batch, d1, d1_bs, ahat, ah_bs); break;
+    case 3: hipLaunchKernelGGL(unsplit_chain_kernel<3>, dim3(grid), dim3(256), 0, s, c, batch, d1, d1_bs, ahat, ah_bs); break;
+    case 4: hipLaunchKernelGGL(unsplit_chain_kernel<4>, dim3(grid), dim3(256), 0, s, c, batch, d1, d1_bs, ahat, ah_bs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace lfft

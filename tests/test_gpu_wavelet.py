@@ -48,6 +48,32 @@ def test_decompose_reconstruct(name, M, J, levels, batch):
     assert rel_l2(xr, W.reconstruct(cz.astype(np.complex128), M, J, levels)) < TOL
 
 
+@pytest.mark.parametrize("name,M,J,levels,batch", [
+    ("large_8", ((4096, 2048), (0, 4096)), workloads.J_QUINCUNX, 8, 1),
+    ("pyramid_7_batch2", ((256, 64), (0, 256)), workloads.J_QUINCUNX, 7, 2),
+    ("jx_5", ((64, 0), (0, 64)), workloads.J_X, 5, 3),
+])
+def test_fused_level_runs_equal_single_levels(name, M, J, levels, batch):
+    """Without `saved` consecutive levels run fused (pairs of levels per launch);
+    with `saved` every level is its own launch.  The fused kernels do the
+    same arithmetic, so the coefficients agree bit for bit; the two
+    reconstructions route their channel FFTs differently and agree to
+    rounding."""
+    from paper_1107_5415_amd import lfft
+    m = abs(L.det(M))
+    print("case", name, flush=True)
+    x = _dev(workloads.complex_normal(33, (batch, m)))
+    w = lfft.WaveletPlan(M, J, levels, batch=batch)
+    masks = w.dirichlet_masks("cuda")
+    c_runs = w.decompose(x, masks)
+    c_lvls = w.decompose(x, masks, saved=w.new_saved(x.device))
+    assert torch.equal(c_runs, c_lvls)
+    x_runs = w.reconstruct(c_runs, masks)
+    x_lvls = w.reconstruct(c_runs, masks, saved=w.new_saved(x.device))
+    assert rel_l2(x_runs.cpu().numpy(), x_lvls.cpu().numpy()) < 1e-6
+    assert rel_l2(x_runs.cpu().numpy(), x.cpu().numpy()) < 2e-5
+
+
 def test_large_eight_levels_full_size():
     """M = [[4096, 2048], [0, 4096]], 8 quincunx levels, Dirichlet masks."""
     from paper_1107_5415_amd import lfft
