@@ -25,6 +25,8 @@ Modules
            general q) with the Dirichlet mask of any q and a Householder
            completion of the wavelet channels, its pyramid, and the
            time-domain definition it must equal
+  scaling  the per-level scaling report of Theorem 3 (pattern dimensions,
+           the step's direction) with brute-force pins
   grad     float64 torch autograd re-implementation for gradient checks
 
 Parity status of every function is stated in its docstring; functions without
