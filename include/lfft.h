@@ -159,6 +159,18 @@ int lwt_plan_destroy(lwt_plan_t plan);
  * elementary divisors of N_l (host outputs, any may be NULL). */
 int lwt_level_info(lwt_plan_t plan, int level, int64_t* N, int64_t* m_level, int64_t* eps_N);
 
+/* Scaling step of level l (Section 5.2, Theorem 3), for a dilation whose
+ * pattern P(J) is cyclic (d_J = 1; UNSUPPORTED otherwise).  Host outputs,
+ * any may be NULL: d_M, d_N, the pattern dimensions of M_l and N_l
+ * (d_M = d_N + 1: the step adds a cycle; d_M = d_N: it grows one); key[d],
+ * the natural sample key in G(M_l) of the step's direction N_l^{-1} z, where
+ * z = J^{-1} g and g is the first key of G(J) in the natural order of the
+ * Hermite box of J whose class generates G(J) (the direction is a class
+ * modulo P(N_l); this representative has key g reduced into the Hermite box
+ * of M_l); grid[d], its coordinates Q^{-1} key mod eps in the forward Smith
+ * basis of M_l (0 on trivial axes), the basis lfft_index_map uses. */
+int lwt_level_scaling(lwt_plan_t plan, int level, int* d_M, int* d_N, int64_t* key, int64_t* grid);
+
 /* Dirichlet scaling mask of level l (Section 6.2): host float[m_l] in
  * NATURAL order of G(M_l^T); values sqrt(q) 2^{(r_M - r_N)/2} (the quotient
  * of the Dirichlet kernels' coefficients; 2^{(1 + r_M - r_N)/2} for q = 2) on

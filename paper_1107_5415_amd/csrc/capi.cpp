@@ -186,6 +186,22 @@ int lwt_level_info(lwt_plan_t plan, int level, int64_t* N, int64_t* m_level, int
   return LFFT_OK;
 }
 
+int lwt_level_scaling(lwt_plan_t plan, int level, int* d_M, int* d_N, int64_t* key,
+                      int64_t* grid) {
+  if (!plan || !plan->w || level < 0 || level >= plan->w->levels) return LFFT_E_ARG;
+  int dm = 0, dn = 0;
+  lfft::i64 k[lfft::kMaxD] = {}, g[lfft::kMaxD] = {};
+  const int st = guarded([&] { lfft::level_scaling(plan->w, level, dm, dn, k, g); });
+  if (st != LFFT_OK) return st;
+  if (d_M) *d_M = dm;
+  if (d_N) *d_N = dn;
+  for (int i = 0; i < plan->w->d; ++i) {
+    if (key) key[i] = k[i];
+    if (grid) grid[i] = g[i];
+  }
+  return LFFT_OK;
+}
+
 int lwt_dirichlet_mask(lwt_plan_t plan, int level, float* mask) {
   if (!plan || !plan->w || !mask || level < 0 || level >= plan->w->levels) return LFFT_E_ARG;
   return guarded([&] { lfft::dirichlet_mask(plan->w, level, mask); });

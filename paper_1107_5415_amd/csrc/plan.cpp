@@ -1116,4 +1116,63 @@ void dirichlet_mask(const WavePlan* w, int level, float* out) {
   }
 }
 
+void level_scaling(const WavePlan* w, int level, int& d_M, int& d_N, i64* key, i64* grid) {
+  const WaveLevel& L = w->lv[level];
+  const LatticePlan* pM = level == 0 ? w->fftM : w->lv[level - 1].fftN;
+  const Smith& S = pM->Sf;
+  const int d = w->d;
+  d_M = 0;
+  d_N = 0;
+  for (int i = 0; i < d; ++i) {
+    d_M += S.eps[i] > 1;
+    d_N += L.fftN->Sf.eps[i] > 1;
+  }
+  // first key g of G(J) (natural order of the Hermite box of J) whose class
+  // has order q: J^{-1} g = adj(J) g / det J, so the order is the least
+  // common multiple of q / gcd(q, (adj(J) g)_i)
+  const i64 DJ = det(w->J);
+  const i64 q = DJ < 0 ? -DJ : DJ;
+  const Mat adj = adjugate(w->J);
+  Mat HJ, UJ;
+  hnf(w->J, HJ, UJ);
+  auto gcd = [](i64 a, i64 b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+      const i64 t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  Vec4 g = zero4();
+  bool found = false;
+  for (i64 idx = 0; idx < q && !found; ++idx) {
+    i64 r = idx;
+    for (int i = d - 1; i >= 0; --i) {
+      g[i] = r % HJ.a[i][i];
+      r /= HJ.a[i][i];
+    }
+    i64 order = 1;
+    for (int i = 0; i < d; ++i) {
+      i64 c = 0;
+      for (int j = 0; j < d; ++j) c = cadd(c, cmul(adj.a[i][j], g[j]));
+      const i64 oi = q / gcd(q, c);
+      order = order / gcd(order, oi) * oi;
+    }
+    found = order == q;
+  }
+  if (!found) throw StatusError{E_UNSUPPORTED};
+  const Vec4 k = reduce4(pM->HM, g);
+  for (int i = 0; i < d; ++i) {
+    key[i] = k[i];
+    i128 acc = 0;
+    for (int j = 0; j < d; ++j) acc += (i128)S.Qinv.a[i][j] * k[j];
+    const i64 e = S.eps[i];
+    i64 x = (i64)(acc % e);
+    if (x < 0) x += e;
+    grid[i] = x;
+  }
+}
+
 }  // namespace lfft

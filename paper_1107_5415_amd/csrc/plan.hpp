@@ -161,6 +161,12 @@ void upload_wave_plan(WavePlan* w);
 void free_wave_plan(WavePlan* w);
 // Dirichlet scaling mask of level l in natural G(M_l^T) order (Section 6.2)
 void dirichlet_mask(const WavePlan* w, int level, float* out);
+// Scaling step of level l (Section 5.2, Theorem 3; P(J) cyclic): pattern
+// dimensions of M_l and N_l, the natural sample key in G(M_l) of the step's
+// direction N_l^{-1} z (z = J^{-1} g, g the first generating key of G(J) in
+// natural order) and its grid coordinates in the forward Smith basis of M_l.
+// Throws E_UNSUPPORTED when P(J) is not cyclic.
+void level_scaling(const WavePlan* w, int level, int& d_M, int& d_N, i64* key, i64* grid);
 
 // Execution (stream ordered).  bstride_in/out: batch strides in elements.
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid,

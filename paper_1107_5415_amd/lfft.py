@@ -29,7 +29,7 @@ LFFT_MAP_FREQS_T = 3
 EXPORTS = [
     "lfft_plan_create", "lfft_plan_destroy", "lfft_plan_query", "lfft_plan_query_inverse_basis",
     "lfft_plan_info", "lfft_index_map", "lfft_workspace_size", "lfft_forward", "lfft_inverse",
-    "lwt_plan_create", "lwt_plan_destroy", "lwt_level_info", "lwt_dirichlet_mask",
+    "lwt_plan_create", "lwt_plan_destroy", "lwt_level_info", "lwt_level_scaling", "lwt_dirichlet_mask",
     "lwt_workspace_size", "lwt_saved_elems", "lwt_decompose", "lwt_reconstruct",
     "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_trace_begin", "lfft_trace_end",
     "lfft_trace_get", "lfft_strerror", "lfft_batch_create", "lfft_batch_destroy",
@@ -78,6 +78,8 @@ def lib():
             "lwt_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _I64P, _I64P, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32]),
             "lwt_plan_destroy": (ctypes.c_int, [_P]),
             "lwt_level_info": (ctypes.c_int, [_P, ctypes.c_int, _I64P, _I64P, _I64P]),
+            "lwt_level_scaling": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.POINTER(ctypes.c_int), _I64P, _I64P]),
             "lwt_dirichlet_mask": (ctypes.c_int, [_P, ctypes.c_int, _FP]),
             "lwt_workspace_size": (ctypes.c_size_t, [_P]),
             "lwt_saved_elems": (ctypes.c_size_t, [_P]),
@@ -302,6 +304,16 @@ class WaveletPlan:
         if h is not None and h.value and _lib is not None:
             _lib.lwt_plan_destroy(h)
             self._h = None
+
+    def level_scaling(self, level):
+        """Theorem 3 report of level l: dict(d_M, d_N, adds, key, grid)."""
+        dm, dn = ctypes.c_int(), ctypes.c_int()
+        key = np.zeros(self.d, np.int64)
+        grid = np.zeros(self.d, np.int64)
+        _check(lib().lwt_level_scaling(self._h, int(level), ctypes.byref(dm), ctypes.byref(dn),
+                                       _ptr64(key), _ptr64(grid)), "lwt_level_scaling")
+        return dict(d_M=dm.value, d_N=dn.value, adds=dm.value - dn.value,
+                    key=tuple(int(v) for v in key), grid=tuple(int(v) for v in grid))
 
     def dirichlet_mask(self, level):
         out = np.zeros(self.level_m[level], np.float32)

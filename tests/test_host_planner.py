@@ -9,6 +9,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+from oracle import scaling as SC
 from oracle import wavelet_q as WQ
 from oracle import lattice as L, wavelet as W
 import workloads
@@ -187,6 +188,44 @@ def test_wavelet_q_levels_and_masks(M, J, levels):
         ref = WQ.dirichlet_mask(Ml, Nl).astype(np.float32)
         assert np.array_equal(w.dirichlet_mask(l), ref)
     assert w.coeff_blocks() == WQ.coeff_layout(M, J, levels)
+
+
+@pytest.mark.parametrize("M,J,levels", [
+    (((2, 0), (0, 2)), workloads.J_X, 1),
+    (((6, 0), (0, 1)), workloads.J_X, 1),
+    (((1, 4), (1, -4)), workloads.J_QUINCUNX, 1),
+    (((32, 8), (-8, 32)), workloads.J_QUINCUNX, 5),
+    (((4096, 2048), (0, 4096)), workloads.J_QUINCUNX, 8),
+    (((16, 0), (0, 16)), workloads.J_D, 6),
+    (((4, -3), (4, 5)), workloads.J_D, 1),
+    (((6, 2, 0), (0, 4, 2), (0, 0, 6)), ((2, 0, 0), (0, 1, 0), (0, 0, 1)), 1),
+    (((27, 9), (0, 9)), ((3, 0), (0, 1)), 2),
+    (((12, 0), (0, 12)), ((2, 1), (0, 2)), 1),
+])
+def test_level_scaling_report(M, J, levels):
+    """Theorem 3 report of every level against the oracle; the grid
+    coordinates agree with the plan's own natural-to-grid sample map."""
+    w = lfft.WaveletPlan(M, J, levels, host_only=True)
+    for l, (Ml, Nl) in enumerate(W.level_matrices(M, J, levels)):
+        r = w.level_scaling(l)
+        d_M, d_N, key = SC.level_scaling(Ml, J)
+        assert (r["d_M"], r["d_N"], r["key"]) == (d_M, d_N, key)
+        assert r["adds"] in (0, 1)
+        p = lfft.LatticePlan(Ml, host_only=True)
+        eps = p.query()["eps"]
+        HM, _ = L.hnf(L.as_matrix(Ml))
+        lin = int(p.index_map(0)[L.box_index(HM, key)])
+        digits = []
+        for e in reversed([int(e) for e in eps if e > 1]):
+            digits.append(lin % e)
+            lin //= e
+        assert tuple(reversed(digits)) == tuple(g for g, e in zip(r["grid"], eps) if e > 1)
+        assert all(g == 0 for g, e in zip(r["grid"], eps) if e == 1)
+
+
+def test_level_scaling_needs_a_cyclic_dilation():
+    w = lfft.WaveletPlan(((8, 0), (0, 8)), ((2, 0), (0, 2)), 1, host_only=True)
+    assert _err(lambda: w.level_scaling(0)) == -5
 
 
 def test_wavelet_masks_large_level_chain():
