@@ -575,6 +575,16 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
     build_engine(p, p->fwd, fs, ff, -1, tw);
     build_engine(p, p->inv_grid, ff, fs, +1, tw);
     build_engine(p, p->inv_nat, is, iff, +1, tw);
+    bool posts = false;
+    for (const auto& R : p->ranges) posts |= R.post;
+    if (p->Sf_aligned && !p->Si_aligned && !posts && p->ranges.size() >= 2 && p->tile_lg == 0) {
+      // the axes are independent DFTs, so their order is free
+      const auto ranges = p->ranges;
+      std::reverse(p->ranges.begin(), p->ranges.end());
+      build_engine(p, p->inv_rev, ff, fs, +1, tw);
+      p->ranges = ranges;
+      p->has_inv_rev = true;
+    }
   } catch (const StatusError&) {
     delete p;
     throw;
@@ -598,6 +608,7 @@ void upload_plan(LatticePlan* p) {
   patch_engine(p->fwd, base);
   patch_engine(p->inv_grid, base);
   patch_engine(p->inv_nat, base);
+  if (p->has_inv_rev) patch_engine(p->inv_rev, base);
 }
 
 void free_plan(LatticePlan* p) {
@@ -641,7 +652,9 @@ void natural_to_grid(const LatticePlan* p, int which, i64* out) {
 
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid, const void* in,
                   void* out, void* ws, long long bin, long long bout, hipStream_t s) {
-  const Engine& E = !inverse ? p->fwd : ((in_grid || out_grid) ? p->inv_grid : p->inv_nat);
+  const Engine& E = !inverse ? p->fwd
+                             : ((in_grid || out_grid) ? p->inv_grid
+                                                      : (p->has_inv_rev ? p->inv_rev : p->inv_nat));
   const int np = (int)E.passes.size();
   for (int i = 0; i < np; ++i) {
     PassDesc pd = E.passes[i];

@@ -90,6 +90,11 @@ struct LatticePlan {
   std::vector<Digit> digits;
   std::vector<PassRange> ranges;
   Engine fwd, inv_nat, inv_grid;
+  // natural -> natural inverse on the forward basis with the passes in
+  // reverse order (built when only the forward basis is aligned and no axis
+  // is split four-step): the last pass writes the aligned sample rows
+  Engine inv_rev;
+  bool has_inv_rev = false;
   Blob blob;
   void* dtab = nullptr;     // device copy of blob
   size_t ws_elems = 0;      // workspace (complex64 elements) per call
