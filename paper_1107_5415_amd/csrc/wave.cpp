@@ -60,11 +60,6 @@ void join(const WavePlan* w, hipStream_t s) {
   check(hipStreamWaitEvent(s, w->ev_join, 0));
 }
 
-// Ping-pong buffer written by level l of an inverse pyramid walk (levels
-// L-1 .. 0): level 0 writes F0 and reads F1, and consecutive levels alternate,
-// so a level never writes the buffer it reads.
-float2* synth_target(const Bufs& b, int l) { return (l == 0 || l % 2 == 0) ? b.F0 : b.F1; }
-
 // algorithmic bytes of one split/unsplit level: read 8 B and write 8 B per
 // complex point and batch element, plus 4 B of mask per point
 double split_bytes(long long B, long long ml) { return (16.0 * (double)B + 4.0) * (double)ml; }
@@ -333,40 +328,32 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
     decompose_runs(w, x, masks, coeffs, ws, s);
     return;
   }
+  // With `saved` (differentiation): one launch per level, the Fourier input
+  // of level l kept in saved at offset sum_{j<l} B m_j (batch stride m_l).
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
-  // Fourier data of level l lives in `cur` with batch stride m_l
-  float2* cur = saved ? saved : b.F0;
-  exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
   const bool batched = w->chan_dec != nullptr;
+  float2* cur = saved;
+  exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
   long long soff = 0;
   bool forked = false;
   for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;
-    const bool small = batched && l >= w->small_from;
-    float2* next;
-    if (saved && l + 1 < L) {
-      next = saved + soff + B * V.ml;
-    } else if (small && l + 1 == L) {
-      next = b.ST + w->stage_d1;
-    } else {
-      next = (cur == b.F0) ? b.F1 : b.F0;
-    }
-    const bool big = l < w->small_from;
-    float2* d2 = small ? b.ST + w->stage_lvl[l] : (big ? b.BD + w->big_d2[l] : b.D2);
+    float2* next = l + 1 < L ? saved + soff + B * V.ml : (batched ? b.ST + w->stage_d1 : b.F0);
+    float2* d2 = d2_slot(w, b, l);
     {
       TraceScope ts("split_kernel", split_bytes(B, V.ml), s);
       check(launch_split(V.sd, B, cur, V.ml, masks[l], next, d2, half, s));
     }
-    if (big) {
-      // the channel FFT overlaps the next splits
+    if (l < w->small_from) {
+      // the large channel's FFT overlaps the next splits
       fork(w, w->ev[l], s);
       forked = true;
       exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW2, half, m,
                    w->s2);
-    } else if (!small) {
+    } else if (!batched) {
       exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
     }
     soff += B * V.ml;
@@ -394,10 +381,11 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     reconstruct_runs(w, coeffs, masks, x, ws, s);
     return;
   }
+  // With `saved` (differentiation): one stream, one launch per level; the
+  // (d1hat, d2hat) of level l are kept in saved at offset sum_{j<l} B m_j.
   Bufs b = carve(w, ws);
   const long long B = w->batch, m = w->m;
   const int L = w->levels;
-  // saved slots (d1hat, d2hat) per level, level-major
   std::vector<long long> soff(L, 0);
   {
     long long o = 0;
@@ -407,56 +395,15 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     }
   }
   const WaveLevel& VL = w->lv[L - 1];
-  // the batched channel launch is used without `saved` (the autograd path
-  // keeps every level's Fourier data in `saved` instead)
-  const bool batched = w->chan_rec != nullptr && !saved;
-  float2* cur;
-  if (saved) {
-    cur = saved + soff[L - 1];
-  } else if (batched) {
-    cur = b.ST + w->stage_d1;
-  } else {
-    // level L-1 reads the buffer level L would have written
-    cur = synth_target(b, L);
-  }
-  // large channels: forward FFTs on the second stream, issued in the order the
-  // unsplits need them (level small_from-1 first); level l's event marks its
-  // completion.  Without `saved` only.
-  const bool ahead = !saved && w->small_from > 0;
-  if (ahead) {
-    fork(w, w->ev_join, s);
-    for (int l = w->small_from - 1; l >= 0; --l) {
-      const WaveLevel& V = w->lv[l];
-      exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), b.BD + w->big_d2[l],
-                   b.FW2, m, V.ml / 2, w->s2);
-      check(hipEventRecord(w->ev[l], w->s2));
-    }
-  }
-  if (batched) {
-    exec_batch(w->chan_rec, false, BATCH_PERSISTENT, coeffs, b.ST, b.FW, s);
-  } else {
-    exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset(w, L), cur, b.FW, m,
-                 VL.ml / 2, s);
-  }
+  float2* cur = saved + soff[L - 1];
+  exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset(w, L), cur, b.FW, m, VL.ml / 2,
+               s);
   for (int l = L - 1; l >= 0; --l) {
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;
-    const bool small = batched && l >= w->small_from;
-    const bool big = ahead && l < w->small_from;
-    float2* d2 = saved ? saved + soff[l] + B * half
-                       : (small ? b.ST + w->stage_lvl[l] : (big ? b.BD + w->big_d2[l] : b.D2));
-    if (big)
-      check(hipStreamWaitEvent(s, w->ev[l], 0));
-    else if (!small)
-      exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), d2, b.FW, m, half, s);
-    float2* next;
-    if (l == 0) {
-      next = b.F0;
-    } else if (saved) {
-      next = saved + soff[l - 1];
-    } else {
-      next = synth_target(b, l);
-    }
+    float2* d2 = saved + soff[l] + B * half;
+    exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), d2, b.FW, m, half, s);
+    float2* next = l == 0 ? b.F0 : saved + soff[l - 1];
     {
       TraceScope ts("unsplit_kernel", split_bytes(B, V.ml), s);
       check(launch_unsplit(V.sd, B, cur, d2, half, masks[l], next, V.ml, s));
