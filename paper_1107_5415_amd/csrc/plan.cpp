@@ -25,7 +25,7 @@ constexpr i64 kMaxTile = 8192;     // elements of one single-pass tile
 constexpr i64 kTileTarget = 4096;  // elements per tile for short pencils
 // pyramid levels whose channel (all signals) has at most this many points
 // run their channel FFTs in one batched launch
-constexpr i64 kChannelBatchElems = i64(1) << 19;
+constexpr i64 kChannelBatchElems = i64(1) << 22;
 
 Vec4 zero4() { return Vec4{0, 0, 0, 0}; }
 
@@ -1014,10 +1014,14 @@ void build_channel_batches(WavePlan* w) {
     add(w->lv[l].Nl, w->lv[l].ml / 2, w->stage_lvl[l], coeff_off[l]);
   add(w->lv[w->levels - 1].Nl, w->lv[w->levels - 1].ml / 2, w->stage_d1, coeff_off[w->levels]);
   const int count = (int)st.size();
+  // tiles of 2^13 elements; the inverse channels (decomposition) take their
+  // leading chunk first, the forward ones (reconstruction) their smallest
+  // radix first (the fastest of the measured schedules on 2^16 .. 2^22
+  // point channels)
   w->chan_dec = build_batch_plan_at(count, d, Ms.data(), st.data(), co.data(), wo.data(),
-                                    (size_t)wsx, 0, 12, 0);
+                                    (size_t)wsx, 0, 13, 1);
   w->chan_rec = build_batch_plan_at(count, d, Ms.data(), co.data(), st.data(), wo.data(),
-                                    (size_t)wsx, 0, 12, 0);
+                                    (size_t)wsx, 0, 13, 2);
 }
 }  // namespace
 
