@@ -935,22 +935,23 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
       fws = std::max(fws, L.fftN->ws_elems);
       if (L.fftW) fws = std::max(fws, L.fftW->ws_elems);
     }
-    // small levels: batch * m_l / 2 at most kChannelBatchElems points (q = 2;
-    // the q > 2 pyramid runs its levels in order on one stream)
+    // small levels: their q - 1 wavelet channels (all signals) hold at most
+    // kChannelBatchElems points
     w->small_from = levels;
-    while (q == 2 && w->small_from > 0 &&
-           batch * (w->lv[w->small_from - 1].ml / 2) <= kChannelBatchElems)
+    while (w->small_from > 0 &&
+           batch * (q - 1) * (w->lv[w->small_from - 1].ml / q) <= kChannelBatchElems)
       --w->small_from;
     size_t chan_ws = 0;
     w->stage_lvl.assign(levels, 0);
     if (w->small_from < levels) {
+      // staging of level l: [B][q-1][m_l/q]; then the final low-pass [B][m_L/q]
       i64 o = 0;
       for (int l = w->small_from; l < levels; ++l) {
         w->stage_lvl[l] = o;
-        o += batch * (w->lv[l].ml / 2);
+        o += batch * (q - 1) * (w->lv[l].ml / q);
       }
       w->stage_d1 = o;
-      o += batch * (w->lv[levels - 1].ml / 2);
+      o += batch * (w->lv[levels - 1].ml / q);
       w->stage_elems = (size_t)o;
       chan_ws = (size_t)o;   // one workspace slot per channel signal
     }
@@ -984,35 +985,40 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
 }
 
 namespace {
-// Batched channel plans: one lattice per (small level, signal) and one per
-// signal for the final low-pass channel.  dec: staging -> coefficients
-// (inverse FFTs), rec: coefficients -> staging (forward FFTs).
+// Batched channel plans: one lattice per (small level, signal, wavelet
+// channel) and one per signal for the final low-pass channel.  dec: staging
+// -> coefficients (inverse FFTs), rec: coefficients -> staging (forward
+// FFTs).
 void build_channel_batches(WavePlan* w) {
   if (w->small_from >= w->levels) return;
   const int d = w->d;
-  const i64 B = w->batch;
+  const i64 B = w->batch, q = w->q;
   std::vector<i64> Ms, st, co, wo;
   i64 coff = 0;
   std::vector<i64> coeff_off(w->levels + 1, 0);
   for (int l = 0; l < w->levels; ++l) {
     coeff_off[l] = coff;
-    coff += w->lv[l].ml / 2;
+    coff += (q - 1) * (w->lv[l].ml / q);
   }
   coeff_off[w->levels] = coff;
   i64 wsx = 0;
-  auto add = [&](const Mat& N, i64 half, i64 stage, i64 cblock) {
+  // ch channels of n points per signal, [B][ch][n] in the staging area and
+  // ch consecutive blocks of the signal's coefficients
+  auto add = [&](const Mat& N, i64 n, i64 ch, i64 stage, i64 cblock) {
     for (i64 b = 0; b < B; ++b) {
-      for (int i = 0; i < d; ++i)
-        for (int j = 0; j < d; ++j) Ms.push_back(N.a[i][j]);
-      st.push_back(stage + b * half);
-      co.push_back(b * w->m + cblock);
-      wo.push_back(wsx);
-      wsx += half;
+      for (i64 j = 0; j < ch; ++j) {
+        for (int r = 0; r < d; ++r)
+          for (int c = 0; c < d; ++c) Ms.push_back(N.a[r][c]);
+        st.push_back(stage + (b * ch + j) * n);
+        co.push_back(b * w->m + cblock + j * n);
+        wo.push_back(wsx);
+        wsx += n;
+      }
     }
   };
   for (int l = w->small_from; l < w->levels; ++l)
-    add(w->lv[l].Nl, w->lv[l].ml / 2, w->stage_lvl[l], coeff_off[l]);
-  add(w->lv[w->levels - 1].Nl, w->lv[w->levels - 1].ml / 2, w->stage_d1, coeff_off[w->levels]);
+    add(w->lv[l].Nl, w->lv[l].ml / q, q - 1, w->stage_lvl[l], coeff_off[l]);
+  add(w->lv[w->levels - 1].Nl, w->lv[w->levels - 1].ml / q, 1, w->stage_d1, coeff_off[w->levels]);
   const int count = (int)st.size();
   // tiles of 2^13 elements; the inverse channels (decomposition) take their
   // leading chunk first, the forward ones (reconstruction) their smallest

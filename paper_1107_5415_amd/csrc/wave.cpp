@@ -236,14 +236,17 @@ size_t wave_saved_elems(const WavePlan* w) {
 // ---------------------------------------------------------------------------
 // q = |det J| > 2: coefficients [B][m] = [lvl 1: ch 1 | .. | ch q-1] ..
 // [lvl L: ch 1 | .. | ch q-1] [ch 0 of lvl L], each block in natural sample
-// order of N_l.  Workspace: F0 (B m), F1 (B m / q), D (B (q-1) m / q), FW.
-// The levels run in order on the caller's stream.
+// order of N_l.  Workspace: F0 (B m), F1 (B m / q), D (B (q-1) m / q), FW,
+// staging.  The levels run in order on the caller's stream; the channels of
+// the small levels and the final low-pass channel go through the staging
+// area and one batched launch pair, the others through D one level at a time.
 namespace {
 struct QBufs {
   float2* F0;
   float2* F1;
   float2* D;
   float2* FW;
+  float2* ST;
 };
 
 QBufs carve_q(const WavePlan* w, void* ws) {
@@ -254,6 +257,7 @@ QBufs carve_q(const WavePlan* w, void* ws) {
   b.F1 = base + bm;
   b.D = b.F1 + bm / w->q;
   b.FW = base + 2 * bm;
+  b.ST = b.FW + w->fw_elems;
   return b;
 }
 
@@ -273,25 +277,35 @@ void decompose_q(const WavePlan* w, const float2* x, const float* const* masks, 
                  void* ws, hipStream_t s) {
   QBufs b = carve_q(w, ws);
   const long long B = w->batch, m = w->m, q = w->q;
+  const int L = w->levels;
+  const bool batched = w->chan_dec != nullptr;
   exec_lattice(w->fftM, false, false, false, x, b.F0, b.FW, m, m, s);
   float2* cur = b.F0;
-  for (int l = 0; l < w->levels; ++l) {
+  for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
     const long long n = V.ml / q;
-    float2* next = cur == b.F0 ? b.F1 : b.F0;
+    const bool small = batched && l >= w->small_from;
+    float2* next = (batched && l + 1 == L) ? b.ST + w->stage_d1 : (cur == b.F0 ? b.F1 : b.F0);
+    float2* dw = small ? b.ST + w->stage_lvl[l] : b.D;
     {
       TraceScope ts("split_q_kernel", split_q_bytes(B, V.ml), s);
-      check(launch_split_q(V.sq, B, cur, V.ml, masks[l], next, n, b.D, (q - 1) * n, s));
+      check(launch_split_q(V.sq, B, cur, V.ml, masks[l], next, n, dw, (q - 1) * n, s));
     }
-    const long long off = coeff_offset_q(w, l);
-    for (long long i = 0; i < B; ++i)
-      exec_lattice(V.fftW, true, false, false, b.D + i * (q - 1) * n, coeffs + i * m + off, b.FW,
-                   n, n, s);
+    if (!small) {
+      const long long off = coeff_offset_q(w, l);
+      for (long long i = 0; i < B; ++i)
+        exec_lattice(V.fftW, true, false, false, b.D + i * (q - 1) * n, coeffs + i * m + off, b.FW,
+                     n, n, s);
+    }
     cur = next;
   }
-  const WaveLevel& VL = w->lv[w->levels - 1];
-  exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset_q(w, w->levels), b.FW,
-               VL.ml / q, m, s);
+  if (batched) {
+    exec_batch(w->chan_dec, true, BATCH_PERSISTENT, b.ST, coeffs, b.FW, s);
+  } else {
+    const WaveLevel& VL = w->lv[L - 1];
+    exec_lattice(VL.fftN, true, false, false, cur, coeffs + coeff_offset_q(w, L), b.FW, VL.ml / q,
+                 m, s);
+  }
 }
 
 void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* masks, float2* x,
@@ -299,19 +313,32 @@ void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* 
   QBufs b = carve_q(w, ws);
   const long long B = w->batch, m = w->m, q = w->q;
   const int L = w->levels;
+  const bool batched = w->chan_rec != nullptr;
   const WaveLevel& VL = w->lv[L - 1];
-  exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset_q(w, L), q_target(b, L), b.FW,
-               m, VL.ml / q, s);
+  float2* cur;
+  if (batched) {
+    exec_batch(w->chan_rec, false, BATCH_PERSISTENT, coeffs, b.ST, b.FW, s);
+    cur = b.ST + w->stage_d1;
+  } else {
+    cur = q_target(b, L);
+    exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset_q(w, L), cur, b.FW, m,
+                 VL.ml / q, s);
+  }
   for (int l = L - 1; l >= 0; --l) {
     const WaveLevel& V = w->lv[l];
     const long long n = V.ml / q;
-    const long long off = coeff_offset_q(w, l);
-    for (long long i = 0; i < B; ++i)
-      exec_lattice(V.fftW, false, false, false, coeffs + i * m + off, b.D + i * (q - 1) * n, b.FW,
-                   n, n, s);
+    const bool small = batched && l >= w->small_from;
+    float2* dw = small ? b.ST + w->stage_lvl[l] : b.D;
+    if (!small) {
+      const long long off = coeff_offset_q(w, l);
+      for (long long i = 0; i < B; ++i)
+        exec_lattice(V.fftW, false, false, false, coeffs + i * m + off, b.D + i * (q - 1) * n, b.FW,
+                     n, n, s);
+    }
+    float2* next = q_target(b, l);
     TraceScope ts("unsplit_q_kernel", split_q_bytes(B, V.ml), s);
-    check(launch_unsplit_q(V.sq, B, q_target(b, l + 1), n, b.D, (q - 1) * n, masks[l],
-                           q_target(b, l), V.ml, s));
+    check(launch_unsplit_q(V.sq, B, cur, n, dw, (q - 1) * n, masks[l], next, V.ml, s));
+    cur = next;
   }
   exec_lattice(w->fftM, true, false, false, b.F0, x, b.FW, m, m, s);
 }

@@ -74,6 +74,26 @@ def test_fused_level_runs_equal_single_levels(name, M, J, levels, batch):
     assert rel_l2(x_runs.cpu().numpy(), x.cpu().numpy()) < 2e-5
 
 
+def test_batched_channels_batch16():
+    """M = [[1024, 256], [0, 1024]] (m = 2^20), batch 16, 4 quincunx levels:
+    level 0's channel (2^23 points over the batch) runs on the second stream,
+    levels 1-3 and the final channel in one batched launch pair; both against
+    the FP64 oracle."""
+    from paper_1107_5415_amd import lfft
+    cfg = workloads.CONFIGS["grad"]
+    M, J, levels, B = cfg["M"], cfg["J"], cfg["levels"], cfg["batch"]
+    m = 1 << 20
+    x = workloads.complex_normal(cfg["seed"], (B, m))
+    w = lfft.WaveletPlan(M, J, levels, batch=B)
+    masks = w.dirichlet_masks("cuda")
+    c = w.decompose(_dev(x), masks)
+    ref = W.decompose(x.astype(np.complex128), M, J, levels)
+    assert rel_l2(c.cpu().numpy(), ref) < TOL
+    del ref
+    xr = w.reconstruct(c, masks).cpu().numpy()
+    assert rel_l2(xr, x) < 2e-5
+
+
 def test_large_eight_levels_full_size():
     """M = [[4096, 2048], [0, 4096]], 8 quincunx levels, Dirichlet masks."""
     from paper_1107_5415_amd import lfft
