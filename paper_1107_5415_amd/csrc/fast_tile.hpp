@@ -191,12 +191,13 @@ __device__ __forceinline__ void apply_tw(float2* x, const float2* b, int sign) {
   for (int i = 1; i < R; ++i) x[i] = c_mul(x[i], pw[i]);
 }
 
+// tw: the stage has twiddles (Ns > 1; the first stage of a digit has none)
 template <int P, int R>
-__device__ __forceinline__ void compute_stage(float2* v, const float2* twb, int sign) {
+__device__ __forceinline__ void compute_stage(float2* v, const float2* twb, int sign, bool tw) {
   constexpr int LG = R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
 #pragma unroll
   for (int q = 0; q < P / R; ++q) {
-    apply_tw<R>(&v[q * R], &twb[q * LG], sign);
+    if (tw) apply_tw<R>(&v[q * R], &twb[q * LG], sign);
     dftR<R>(&v[q * R], sign);
   }
 }
@@ -260,6 +261,9 @@ __device__ __forceinline__ void store_last_r(const float2* v, const PassDesc& p,
   const StageDesc& st = p.st[p.nst - 1];
   float2* out = const_cast<float2*>(A.base);
   const bool scaled = p.scale != 1.0f;
+  // four-step twiddle exponent ((l mod post_lmod) * lo) mod postN, lo fixed
+  // per pencil
+  const long long lo = p.post ? (pc.s / p.lo_div) % p.lo_n : 0;
 #pragma unroll
   for (int q = 0; q < P / R; ++q) {
     BfGeom g = geom(st, jt + TPP * q);
@@ -267,7 +271,6 @@ __device__ __forceinline__ void store_last_r(const float2* v, const PassDesc& p,
       float2 x = v[q * R + i];
       if (p.post) {
         const int l = (g.out0 + i * g.out_step) % p.post_lmod;
-        const long long lo = (pc.s / p.lo_div) % p.lo_n;
         const long long t = ((long long)l * lo) % p.postN;
         float2 w = c_mul(p.tw_hi[t >> 12], p.tw_lo[t & 4095]);
         if (p.sign > 0) w.y = -w.y;
@@ -322,13 +325,14 @@ __device__ __forceinline__ void fast_tile(const PassDesc& p, long long tile, int
     LFFT_RADIX_SWITCH(p.st[0].radix, (load_first<P, RR, MIN>(v, p, A, jt, TPP, pc.active)));
   }
   float2 twb[8];
-  LFFT_RADIX_SWITCH(p.st[0].radix, (prefetch_tw<P, RR>(twb, p.st[0], jt, TPP)));
+  if (p.st[0].Ns > 1)
+    LFFT_RADIX_SWITCH(p.st[0].radix, (prefetch_tw<P, RR>(twb, p.st[0], jt, TPP)));
   for (int si = 0; si < p.nst; ++si) {
     const StageDesc& st = p.st[si];
-    LFFT_RADIX_SWITCH(st.radix, (compute_stage<P, RR>(v, twb, p.sign)));
+    LFFT_RADIX_SWITCH(st.radix, (compute_stage<P, RR>(v, twb, p.sign, st.Ns > 1)));
     if (si + 1 < p.nst) {
       const StageDesc& nx = p.st[si + 1];
-      LFFT_RADIX_SWITCH(nx.radix, (prefetch_tw<P, RR>(twb, nx, jt, TPP)));
+      if (nx.Ns > 1) LFFT_RADIX_SWITCH(nx.radix, (prefetch_tw<P, RR>(twb, nx, jt, TPP)));
       if constexpr (!SPLIT) {
         LFFT_RADIX_SWITCH(st.radix, (lds_write<P, RR, COLS, 0>(v, lds, st, jt, TPP, w, W, L)));
         __syncthreads();
