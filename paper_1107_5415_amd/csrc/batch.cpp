@@ -71,7 +71,7 @@ void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
   for (int i = 0; i < b->count; ++i) {
     LatticePlan* p = b->tiled[i];
     if (!p) continue;
-    const Engine& E = inverse ? p->inv_nat : p->fwd;
+    const Engine& E = inverse ? (p->has_inv_rev ? p->inv_rev : p->inv_nat) : p->fwd;
     const int np = (int)E.passes.size();
     if (np < 1 || np > 2) throw StatusError{E_STATE};
     Inst in{(int)passes.size(), np, b->m[i]};

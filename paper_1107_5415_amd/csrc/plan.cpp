@@ -577,7 +577,7 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
     build_engine(p, p->inv_nat, is, iff, +1, tw);
     bool posts = false;
     for (const auto& R : p->ranges) posts |= R.post;
-    if (p->Sf_aligned && !p->Si_aligned && !posts && p->ranges.size() >= 2 && p->tile_lg == 0) {
+    if (p->Sf_aligned && !p->Si_aligned && !posts && p->ranges.size() >= 2) {
       // the axes are independent DFTs, so their order is free
       const auto ranges = p->ranges;
       std::reverse(p->ranges.begin(), p->ranges.end());
@@ -1020,12 +1020,11 @@ void build_channel_batches(WavePlan* w) {
     add(w->lv[l].Nl, w->lv[l].ml / q, q - 1, w->stage_lvl[l], coeff_off[l]);
   add(w->lv[w->levels - 1].Nl, w->lv[w->levels - 1].ml / q, 1, w->stage_d1, coeff_off[w->levels]);
   const int count = (int)st.size();
-  // tiles of 2^13 elements; the inverse channels (decomposition) take their
-  // leading chunk first, the forward ones (reconstruction) their smallest
-  // radix first (the fastest of the measured schedules on 2^16 .. 2^22
-  // point channels)
+  // tiles of 2^13 elements; the forward channels (reconstruction) take
+  // their smallest radix first (the fastest of the measured schedules on
+  // 2^16 .. 2^22 point channels)
   w->chan_dec = build_batch_plan_at(count, d, Ms.data(), st.data(), co.data(), wo.data(),
-                                    (size_t)wsx, 0, 13, 1);
+                                    (size_t)wsx, 0, 13, 0);
   w->chan_rec = build_batch_plan_at(count, d, Ms.data(), co.data(), st.data(), wo.data(),
                                     (size_t)wsx, 0, 13, 2);
 }

@@ -92,7 +92,8 @@ struct LatticePlan {
   Engine fwd, inv_nat, inv_grid;
   // natural -> natural inverse on the forward basis with the passes in
   // reverse order (built when only the forward basis is aligned and no axis
-  // is split four-step): the last pass writes the aligned sample rows
+  // is split four-step): the last pass writes the aligned sample rows; used
+  // by exec_lattice and by the batched launch
   Engine inv_rev;
   bool has_inv_rev = false;
   Blob blob;
