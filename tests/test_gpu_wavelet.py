@@ -74,6 +74,43 @@ def test_fused_level_runs_equal_single_levels(name, M, J, levels, batch):
     assert rel_l2(x_runs.cpu().numpy(), x.cpu().numpy()) < 2e-5
 
 
+def _random_pyramids():
+    """M = J^L N with a random regular N (so every level is integral), for
+    the quincunx, J_x, J_d and a three-dimensional dilation."""
+    rng = np.random.default_rng(51)
+    out = []
+    dil = [(workloads.J_QUINCUNX, 2), (workloads.J_X, 2), (workloads.J_D, 2),
+           (((1, 0, 0), (0, 2, 0), (0, 0, 1)), 3)]
+    for i in range(8):
+        J, d = dil[i % len(dil)]
+        levels = 2 + i % 4
+        lo, hi, md = ((-9, 10, 4096) if i < 4 else (-200, 201, 40000)) if d == 2 else (-9, 10, 300)
+        N = workloads.random_regular_matrix(rng, d, lo=lo, hi=hi, max_det=md)
+        M = L.as_matrix(N)
+        for _ in range(levels):
+            M = L.matmul(L.as_matrix(J), M)
+        M = tuple(tuple(int(x) for x in row) for row in M)
+        out.append((M, J, levels, 1 + i % 3))
+    return out
+
+
+@pytest.mark.parametrize("M,J,levels,batch", _random_pyramids())
+def test_random_pyramids(M, J, levels, batch):
+    """Random lattices through the fused runs, the batched channels and the
+    reversed inverse, against the FP64 oracle."""
+    from paper_1107_5415_amd import lfft
+    m = abs(L.det(L.as_matrix(M)))
+    print("case", M, J, levels, batch, flush=True)
+    x = workloads.complex_normal(52, (batch, m))
+    w = lfft.WaveletPlan(M, J, levels, batch=batch)
+    masks = w.dirichlet_masks("cuda")
+    c = w.decompose(_dev(x), masks)
+    assert rel_l2(c.cpu().numpy(), W.decompose(x.astype(np.complex128), M, J, levels)) < TOL
+    cz = workloads.complex_normal(53, (batch, m))
+    xr = w.reconstruct(_dev(cz), masks).cpu().numpy()
+    assert rel_l2(xr, W.reconstruct(cz.astype(np.complex128), M, J, levels)) < TOL
+
+
 def test_batched_channels_batch16():
     """M = [[1024, 256], [0, 1024]] (m = 2^20), batch 16, 4 quincunx levels:
     level 0's channel (2^23 points over the batch) runs on the second stream,
