@@ -424,21 +424,38 @@ hipError_t launch_t(const PassDesc& p, const float2* in, float2* out, hipStream_
   return hipGetLastError();
 }
 
-template <int L, int W, bool COLS, bool SPLIT, int MIN>
+// Exchange real and imaginary parts separately when the tile would not fit
+// 72 KB of LDS as complex values, except for the 2048 x 8 column tiles with a
+// natural side: one workgroup per CU holds their 139 KB complex tile, and
+// whole complex exchanges (half the barriers) measured 2% faster on the step
+// without spilling registers.
+__host__ __device__ constexpr bool stream_split(int L, int W, bool cols, int min, int mout) {
+  return (cols && L == 2048 && W == 8 && mout != MAP_LINEAR &&
+          (min == MAP_NATURAL || mout == MAP_NATURAL))
+             ? false
+             : ((cols || kSplitRows) ? ((long long)W * L * 17 / 16 * 8 > 72 * 1024 || kSplitRows)
+                                     : false);
+}
+
+template <int L, int W, bool COLS, int MIN>
 hipError_t launch_o(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
   switch (p.out.mode) {
-    case MAP_IDENTITY: return launch_t<L, W, COLS, SPLIT, MIN, MAP_IDENTITY>(p, in, out, s);
-    case MAP_LINEAR: return launch_t<L, W, COLS, SPLIT, MIN, MAP_LINEAR>(p, in, out, s);
-    default: return launch_t<L, W, COLS, SPLIT, MIN, MAP_NATURAL>(p, in, out, s);
+    case MAP_IDENTITY:
+      return launch_t<L, W, COLS, stream_split(L, W, COLS, MIN, MAP_IDENTITY), MIN, MAP_IDENTITY>(
+          p, in, out, s);
+    case MAP_LINEAR:
+      return launch_t<L, W, COLS, stream_split(L, W, COLS, MIN, MAP_LINEAR), MIN, MAP_LINEAR>(
+          p, in, out, s);
+    default:
+      return launch_t<L, W, COLS, stream_split(L, W, COLS, MIN, MAP_NATURAL), MIN, MAP_NATURAL>(
+          p, in, out, s);
   }
 }
 
 template <int L, int W, bool COLS>
 hipError_t launch_i(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
-  constexpr bool SPLIT = (COLS || kSplitRows) ? ((long long)W * L * 17 / 16 * 8 > 72 * 1024 || kSplitRows)
-                                              : false;
-  if (p.in.mode == MAP_NATURAL) return launch_o<L, W, COLS, SPLIT, MAP_NATURAL>(p, in, out, s);
-  return launch_o<L, W, COLS, SPLIT, MAP_IDENTITY>(p, in, out, s);
+  if (p.in.mode == MAP_NATURAL) return launch_o<L, W, COLS, MAP_NATURAL>(p, in, out, s);
+  return launch_o<L, W, COLS, MAP_IDENTITY>(p, in, out, s);
 }
 
 }  // namespace
@@ -458,10 +475,9 @@ const char* stream_kernel_name(const PassDesc& p) {
   // the template arguments exactly as the profiler prints the symbol
   const bool cols = p.S > 1;
   const int W = p.W;
-  const bool split = (cols || kSplitRows) ? ((long long)W * p.L * 17 / 16 * 8 > 72 * 1024 || kSplitRows)
-                                          : false;
   const int min = p.in.mode == MAP_NATURAL ? 2 : 0;
   const int mout = p.out.mode;
+  const bool split = stream_split(p.L, W, cols, min, mout);
   return kernel_name_intern("fft_stream_kernel<%d, %d, %s, %s, %d, %d>", p.L, W,
                             cols ? "true" : "false", split ? "true" : "false", min, mout);
 }
