@@ -131,6 +131,41 @@ def test_batched_channels_batch16():
     assert rel_l2(xr, x) < 2e-5
 
 
+def test_largest_sizes_m2e28():
+    """m = 2^28 (M = [[16384, 8192], [0, 16384]]): beyond the streaming
+    kernels' 2^28 bound and the 32-bit fiber maps, so the FFT runs on the
+    general register-resident passes (three of them, one four-step) and the
+    split on 64-bit index arithmetic.  Checked by properties that hold at any
+    size (unitarity, inverse, Parseval of the orthogonal pyramid, perfect
+    reconstruction) and by one exact bin of the oracle."""
+    from paper_1107_5415_amd import lfft
+    from oracle import dft
+    M = ((16384, 8192), (0, 16384))
+    m = 1 << 28
+    print("case m = 2^28", flush=True)
+    x = workloads.complex_normal(61, m)
+    xd = _dev(x)
+    plan = lfft.LatticePlan(M)
+    X = plan.forward(xd)
+    nx = torch.linalg.vector_norm(xd.to(torch.complex128)).item()
+    assert abs(torch.linalg.vector_norm(X.to(torch.complex128)).item() / nx - 1) < 1e-5
+    back = plan.inverse(X)
+    assert (torch.linalg.vector_norm((back - xd).to(torch.complex128)).item() / nx) < 2e-5
+    del back
+    h = (12345, 678)
+    HT, _ = L.hnf(L.transpose(L.as_matrix(M)))
+    ref = dft.direct_bins(M, x, [h])[0]
+    got = X[L.box_index(HT, L.reduce_box(HT, h))].item()
+    assert abs(got - ref) < 1e-4
+    del X
+    w = lfft.WaveletPlan(M, workloads.J_QUINCUNX, 1)
+    masks = w.dirichlet_masks("cuda")
+    c = w.decompose(xd, masks)
+    assert abs(torch.linalg.vector_norm(c.to(torch.complex128)).item() / nx - 1) < 1e-5
+    xr = w.reconstruct(c, masks)
+    assert (torch.linalg.vector_norm((xr - xd).to(torch.complex128)).item() / nx) < 2e-5
+
+
 def test_large_eight_levels_full_size():
     """M = [[4096, 2048], [0, 4096]], 8 quincunx levels, Dirichlet masks."""
     from paper_1107_5415_amd import lfft
