@@ -57,6 +57,11 @@ CASES = [
     ("d1_four_step_2^20", ((1 << 20,),), 1),
     ("d1_negative_mixed", ((-360,),), 2),
     ("d1_trivial", ((1,),), 2),
+    # long power-of-two cycles split as 32 x (n / 32)
+    ("d1_split_2^14", ((1 << 14,),), 2),
+    ("d1_split_2^16", ((1 << 16,),), 1),
+    ("split_2^15_plus_axis", ((4, 0), (0, 1 << 15)), 2),
+    ("split_2^17_sheared", ((8, 4), (0, 1 << 17)), 1),
 ]
 
 
