@@ -547,9 +547,18 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       int i = Dg - 1;
       while (i >= 0) {
         if (p->digits[i].part == 2) {
-          p->ranges.push_back(PassRange{i - 1, i, true, p->digits[i].axis});
+          // the high digit closes a pass that also takes the whole axes
+          // before it while they fit one pencil (no pass over a short axis
+          // alone); its four-step twiddle follows the pass
+          int a = i - 1;
+          i64 prod = p->digits[a].n;
+          while (a - 1 >= 0 && p->digits[a - 1].part == 0 && prod * p->digits[a - 1].n <= kMaxPencil) {
+            --a;
+            prod *= p->digits[a].n;
+          }
+          p->ranges.push_back(PassRange{a, i, true, p->digits[i].axis});
           p->ranges.push_back(PassRange{i, i + 1, false, 0});
-          i -= 2;
+          i = a - 1;
         } else {
           int a = i;
           i64 prod = p->digits[i].n;
