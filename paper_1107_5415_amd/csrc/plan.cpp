@@ -538,6 +538,28 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
         }
       }
     }
+    if (tile_lg == 0 && p->m > kMaxTile) {
+      // Leading axes shorter than 32 points in all that cannot share a pass
+      // with the next axis: split that axis four-step so that its high digit
+      // joins them (a pass of at least 32 points on the register-resident
+      // kernels instead of a pass over the short axes alone).
+      size_t k = 0;
+      i64 P = 1;
+      while (k < p->digits.size() && p->digits[k].part == 0 && P * p->digits[k].n < 32) {
+        P *= p->digits[k].n;
+        ++k;
+      }
+      if (k >= 1 && k < p->digits.size() && p->digits[k].part == 0 && is_pow2(P)) {
+        const Digit g = p->digits[k];
+        if (is_pow2(g.n) && P * g.n > kMaxPencil) {
+          const i64 hi = 32 / P, lo = g.n / hi;
+          if (hi >= 2 && lo >= 32) {
+            p->digits[k] = Digit{g.axis, hi, 1, lo, 1};
+            p->digits.insert(p->digits.begin() + (long)k + 1, Digit{g.axis, lo, 2, 1, hi});
+          }
+        }
+      }
+    }
     const int Dg = (int)p->digits.size();
     if (tile_lg > 0) {
       // ranges set by the tiled schedule

@@ -62,6 +62,11 @@ CASES = [
     ("d1_split_2^16", ((1 << 16,),), 1),
     ("split_2^15_plus_axis", ((4, 0), (0, 1 << 15)), 2),
     ("split_2^17_sheared", ((8, 4), (0, 1 << 17)), 1),
+    # a short leading axis joined by the high digit of the next one
+    ("short_axis_4x4096", ((4, 0), (0, 4096)), 3),
+    ("short_axis_2x8192_sheared", ((2, 1), (0, 8192)), 2),
+    ("short_axis_16x2048", ((16, 0), (0, 2048)), 1),
+    ("short_axes_d3", ((2, 0, 0), (0, 4, 0), (0, 0, 4096)), 2),
 ]
 
 
