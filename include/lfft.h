@@ -121,6 +121,22 @@ int lfft_plan_info(lfft_plan_t plan, int* passes, int* aligned_forward, int* ali
  * lambda = Q^{-1} g mod eps, mu = R^{-T} h mod eps).  Bijective. */
 int lfft_index_map(lfft_plan_t plan, int which, int64_t* natural_to_grid);
 
+/* ---- point selectors of lfft_points ----------------------------------- */
+#define LFFT_POINTS_SAMPLES 0    /* keys g of G(M), points y = M^{-1} g       */
+#define LFFT_POINTS_FREQS 1      /* keys h of G(M^T), points M^{-T} h          */
+
+/* Points of one side in NATURAL order (host outputs, m x d row-major each,
+ * either may be NULL).  keys: the integer key of every point, g in the
+ * Hermite box of M for the pattern P(M), h in the Hermite box of M^T for the
+ * generating group G(M^T) (Section 2.2: pattern, generating group).
+ * sym_num: the point's symmetric representative times m, i.e. the integer
+ * vector t with M^{-1} g = t / m (samples) or M^{-T} h = t / m (frequencies)
+ * modulo Z^d, every coordinate reduced into [-m/2, m/2): the representative
+ * in the symmetric pattern Lambda(M) cap [-1/2, 1/2)^d of Section 6.2 (the
+ * frequency side is what the Dirichlet mask is evaluated on).  Exact
+ * (128-bit intermediates).  Errors: ARG (null plan, which not 0 or 1). */
+int lfft_points(lfft_plan_t plan, int which, int64_t* keys, int64_t* sym_num);
+
 /* Workspace bytes needed by lfft_forward / lfft_inverse. */
 size_t lfft_workspace_size(lfft_plan_t plan);
 
@@ -170,6 +186,36 @@ int lwt_level_info(lwt_plan_t plan, int level, int64_t* N, int64_t* m_level, int
  * of M_l); grid[d], its coordinates Q^{-1} key mod eps in the forward Smith
  * basis of M_l (0 on trivial axes), the basis lfft_index_map uses. */
 int lwt_level_scaling(lwt_plan_t plan, int level, int* d_M, int* d_N, int64_t* key, int64_t* grid);
+
+/* Fiber maps of level l (0-based) exactly as the split/unsplit kernels
+ * address them (Section 2.2 eq. decomposition applied to
+ * G(M_l^T) = G(N_l^T) + N_l^T G(J^T); Section 5.3 steps 2-3), for the natural
+ * indices k = k0 .. k0 + count - 1 of G(N_l^T) (host outputs, either may be
+ * NULL):
+ *  lifts[(k - k0) * q + j]: NATURAL index in G(M_l^T) of the fiber member
+ *    k + N_l^T g_j reduced into the Hermite box of M_l^T, g_0 = 0 and, for
+ *    q = 2, g_1 = g0 the nonzero class of G(J^T) (so member 1 is the partner
+ *    h0 + s, s = N_l^T g0); for q > 2 the classes of G(J^T) in the natural
+ *    order of the Hermite box of J^T.  Every class of G(M_l^T) is a member of
+ *    exactly one fiber.
+ *  phase[k - k0] (q = 2 only; must be NULL for q > 2): the residue rho in
+ *    [0, m_l) of the wavelet phase phi(h0) = exp(-2 pi i h0^T M_l^{-1} J y0)
+ *    = exp(-2 pi i rho / m_l), y0 the nonzero point of P(J) in
+ *    [-1/2, 1/2)^d (Section 6.2 wavelet symbol).
+ * path: 0 the kernels' choice for this level, 1 the 32-bit index path
+ * (UNSUPPORTED if the level's bounds exclude it), 2 the 64-bit path.
+ * Errors: ARG (level, path or range out of bounds), UNSUPPORTED. */
+int lwt_fiber_map(lwt_plan_t plan, int level, int path, int64_t k0, int64_t count,
+                  int64_t* lifts, int64_t* phase);
+
+/* Coefficient layout of lwt_decompose (host outputs, any may be NULL):
+ * q = |det J| channels per level, nblocks = levels (q - 1) + 1 blocks, and per
+ * block its element offset and length within one signal's m coefficients,
+ * its level (0-based) and channel (1 .. q-1 wavelet channels, 0 for the
+ * final low-pass block of the last level).  Arrays hold nblocks entries;
+ * call once with NULL arrays to learn nblocks. */
+int lwt_coeff_layout(lwt_plan_t plan, int* q, int* nblocks, int64_t* offset, int64_t* length,
+                     int* level, int* channel);
 
 /* Dirichlet scaling mask of level l (Section 6.2): host float[m_l] in
  * NATURAL order of G(M_l^T); values sqrt(q) 2^{(r_M - r_N)/2} (the quotient

@@ -138,9 +138,11 @@ class TorchPyramid:
         return self.top.inverse(ah)
 
 
-def pyramid_loss(pyr, x, masks, target, weights):
+def pyramid_loss(pyr, x, masks, target, weights, masks_rec=None):
     """sum_l w_l ||d2^(l)||^2 + ||reconstruct(decompose(x)) - target||^2
-    (the differentiation workload's loss; d2 in the time domain)."""
+    (the differentiation workload's loss; d2 in the time domain).
+    masks_rec: the masks the reconstruction uses (default: the same tensors),
+    so the two contributions to a mask gradient can be taken apart."""
     c = pyr.decompose(x, masks)
     sizes = [v["ml"] // 2 for v in pyr.lv]
     offs = np.cumsum([0] + sizes)
@@ -148,16 +150,25 @@ def pyramid_loss(pyr, x, masks, target, weights):
     for l, w in enumerate(weights):
         blk = c[:, offs[l]:offs[l] + sizes[l]]
         loss = loss + w * torch.sum(blk.real ** 2 + blk.imag ** 2)
-    r = pyr.reconstruct(c, masks) - target
+    r = pyr.reconstruct(c, masks if masks_rec is None else masks_rec) - target
     return loss + torch.sum(r.real ** 2 + r.imag ** 2)
 
 
-def loss_and_grads(M, J, levels, x, masks, target, weights):
-    """FP64 loss and autograd gradients w.r.t. x (complex) and the masks."""
+def loss_and_grads(M, J, levels, x, masks, target, weights, parts=False):
+    """FP64 loss and autograd gradients w.r.t. x (complex) and the masks.
+
+    parts=True: the mask gradients are returned as two lists, the
+    contribution through the decomposition and the one through the
+    reconstruction (their sum is the mask gradient)."""
     pyr = TorchPyramid(M, J, levels)
     xt = torch.tensor(np.asarray(x), dtype=torch.complex128, requires_grad=True)
     mt = [torch.tensor(np.asarray(mk), dtype=torch.float64, requires_grad=True) for mk in masks]
+    ms = ([torch.tensor(np.asarray(mk), dtype=torch.float64, requires_grad=True) for mk in masks]
+          if parts else None)
     tt = torch.tensor(np.asarray(target), dtype=torch.complex128)
-    loss = pyramid_loss(pyr, xt, mt, tt, weights)
+    loss = pyramid_loss(pyr, xt, mt, tt, weights, masks_rec=ms)
     loss.backward()
+    if parts:
+        return (float(loss.detach()), xt.grad.numpy(), [m.grad.numpy() for m in mt],
+                [m.grad.numpy() for m in ms])
     return float(loss.detach()), xt.grad.numpy(), [m.grad.numpy() for m in mt]

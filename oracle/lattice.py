@@ -252,6 +252,24 @@ def symmetric_rep_T(M, h):
     return tuple(x // m for x in hs), tuple(t), m
 
 
+def symmetric_rep(M, g):
+    """Symmetric representative of the sample point y = M^{-1} g of P(M).
+
+    The representative of y + Z^d in [-1/2, 1/2)^d (Section 6.2's symmetric
+    pattern), returned as the integer vector t with that point = t/m,
+    m = |det M|: M^{-1} g = sgn(det M) adj(M) g / m, reduced coordinatewise
+    into [-m/2, m/2).  Returns (t, m).
+    """
+    M = as_matrix(M)
+    D = det(M)
+    m = abs(D)
+    A = adjugate(M)
+    d = len(M)
+    half = m // 2
+    t = [sign(D) * sum(A[j][k] * g[k] for k in range(d)) for j in range(d)]
+    return tuple(((x + half) % m) - half for x in t), m
+
+
 def lattice_points_bruteforce(M):
     """Brute-force enumeration of P(M) = M^{-1} Z^d cap [0,1)^d (tiny m only).
 

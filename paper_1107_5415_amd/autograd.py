@@ -99,11 +99,7 @@ def wavelet_reconstruct(c, plan, masks):
 
 
 def channel_blocks(plan):
-    """(offset, length) of every coefficient block [d2^(1) .. d2^(L) | d1^(L)]."""
-    out = []
-    off = 0
-    for ml in plan.level_m:
-        out.append((off, ml // 2))
-        off += ml // 2
-    out.append((off, plan.level_m[-1] // 2))
-    return out
+    """(offset, length) of every coefficient block of one signal, in the
+    library's layout (lwt_coeff_layout): the wavelet channels of every level,
+    then the final low-pass block."""
+    return [(off, n) for (_, _, off, n) in plan.coeff_blocks()]

@@ -130,6 +130,11 @@ int lfft_index_map(lfft_plan_t plan, int which, int64_t* natural_to_grid) {
   return guarded([&] { lfft::natural_to_grid(plan->p, which, natural_to_grid); });
 }
 
+int lfft_points(lfft_plan_t plan, int which, int64_t* keys, int64_t* sym_num) {
+  if (!plan || !plan->p || which < 0 || which > 1) return LFFT_E_ARG;
+  return guarded([&] { lfft::points(plan->p, which, keys, sym_num); });
+}
+
 size_t lfft_workspace_size(lfft_plan_t plan) {
   if (!plan || !plan->p) return 0;
   return plan->p->ws_elems * 8;
@@ -199,6 +204,34 @@ int lwt_level_scaling(lwt_plan_t plan, int level, int* d_M, int* d_N, int64_t* k
     if (key) key[i] = k[i];
     if (grid) grid[i] = g[i];
   }
+  return LFFT_OK;
+}
+
+int lwt_fiber_map(lwt_plan_t plan, int level, int path, int64_t k0, int64_t count,
+                  int64_t* lifts, int64_t* phase) {
+  if (!plan || !plan->w) return LFFT_E_ARG;
+  return guarded([&] { lfft::fiber_map(plan->w, level, path, k0, count, lifts, phase); });
+}
+
+int lwt_coeff_layout(lwt_plan_t plan, int* q, int* nblocks, int64_t* offset, int64_t* length,
+                     int* level, int* channel) {
+  if (!plan || !plan->w) return LFFT_E_ARG;
+  const lfft::WavePlan* w = plan->w;
+  if (q) *q = w->q;
+  if (nblocks) *nblocks = w->levels * (w->q - 1) + 1;
+  int64_t off = 0;
+  int b = 0;
+  auto put_block = [&](int l, int j, int64_t n) {
+    if (offset) offset[b] = off;
+    if (length) length[b] = n;
+    if (level) level[b] = l;
+    if (channel) channel[b] = j;
+    off += n;
+    ++b;
+  };
+  for (int l = 0; l < w->levels; ++l)
+    for (int j = 1; j < w->q; ++j) put_block(l, j, w->lv[l].ml / w->q);
+  put_block(w->levels - 1, 0, w->lv[w->levels - 1].ml / w->q);
   return LFFT_OK;
 }
 

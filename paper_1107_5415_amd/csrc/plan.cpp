@@ -14,6 +14,7 @@
 #include <map>
 
 #include "batch.hpp"
+#include "fiber.hpp"
 #include "kernels.hpp"
 #include "ktrace.hpp"
 
@@ -687,6 +688,38 @@ void natural_to_grid(const LatticePlan* p, int which, i64* out) {
   }
 }
 
+void points(const LatticePlan* p, int which, i64* keys, i64* sym) {
+  // which 0: keys g of G(M) (Hermite box of M), m M^{-1} g = sgn adj(M) g;
+  // which 1: keys h of G(M^T) (Hermite box of M^T), m M^{-T} h = sgn adj(M)^T h.
+  // Every coordinate of the second is reduced into [-m/2, m/2) (the symmetric
+  // pattern Lambda(M) cap [-1/2, 1/2)^d of Section 6.2, scaled by m).
+  const int d = p->d;
+  const bool freq = which == 1;
+  const Mat& H = freq ? p->HMT : p->HM;
+  const Mat A = adjugate(p->M);
+  const i64 D = det(p->M);
+  const i64 sg = D < 0 ? -1 : 1;
+  const i64 m = p->m, half = m / 2;
+  std::vector<i64> v(d, 0);
+  for (i64 idx = 0; idx < m; ++idx) {
+    i64 r = idx;
+    for (int i = d - 1; i >= 0; --i) {
+      v[i] = r % H.a[i][i];
+      r /= H.a[i][i];
+    }
+    for (int j = 0; j < d; ++j) {
+      if (keys) keys[idx * d + j] = v[j];
+      if (!sym) continue;
+      i128 acc = 0;
+      for (int k = 0; k < d; ++k) acc += (i128)(freq ? A.a[k][j] : A.a[j][k]) * v[k];
+      acc *= sg;
+      i128 t = (acc + half) % m;
+      if (t < 0) t += m;
+      sym[idx * d + j] = (i64)t - half;
+    }
+  }
+}
+
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid, const void* in,
                   void* out, void* ws, long long bin, long long bout, hipStream_t s) {
   const Engine& E = !inverse ? p->fwd
@@ -1172,6 +1205,40 @@ void dirichlet_mask(const WavePlan* w, int level, float* out) {
                    : std::sqrt((double)q) * p2;
     }
     out[idx] = (float)val;
+  }
+}
+
+void fiber_map(const WavePlan* w, int level, int path, i64 k0, i64 count, i64* lifts,
+               i64* phase) {
+  if (level < 0 || level >= w->levels || path < 0 || path > 2 || k0 < 0 || count < 0)
+    throw StatusError{E_ARG};
+  const WaveLevel& L = w->lv[level];
+  const i64 q = w->q;
+  if (k0 + count > L.ml / q) throw StatusError{E_ARG};
+  if (q > 2) {
+    if (phase) throw StatusError{E_UNSUPPORTED};
+    const bool narrow = path == 0 ? L.sq.narrow != 0 : path == 1;
+    if (narrow && !L.sq.narrow) throw StatusError{E_UNSUPPORTED};
+    long long idx[kMaxQ];
+    for (i64 c = 0; c < count; ++c) {
+      fib::fiber_q_index<0>(L.sq, k0 + c, idx, narrow);
+      if (lifts)
+        for (i64 l = 0; l < q; ++l) lifts[c * q + l] = idx[l];
+    }
+    return;
+  }
+  const SplitDesc& sd = L.sd;
+  const bool narrow = path == 0 ? sd.narrow != 0 : path == 1;
+  if (narrow && !sd.narrow) throw StatusError{E_UNSUPPORTED};
+  // phi(h0) = exp(-2 pi i rho / E) = exp(-2 pi i (rho m_l / E) / m_l)
+  const i64 scale = L.ml / sd.E;
+  for (i64 c = 0; c < count; ++c) {
+    const fib::FiberIdx f = narrow ? fib::fiber_index32(sd, k0 + c) : fib::fiber_index64(sd, k0 + c);
+    if (lifts) {
+      lifts[2 * c] = f.i0;
+      lifts[2 * c + 1] = f.i1;
+    }
+    if (phase) phase[c] = f.rho * scale;
   }
 }
 

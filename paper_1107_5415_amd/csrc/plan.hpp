@@ -114,6 +114,12 @@ void free_plan(LatticePlan* p);
 // FREQS: mu = R^{-T} h mod eps, in the forward basis).
 void natural_to_grid(const LatticePlan* p, int which, i64* out);
 
+// Natural keys and symmetric representatives of the points of one side
+// (which 0: samples, keys g of G(M) and m M^{-1} g; which 1: frequencies,
+// keys h of G(M^T) and m M^{-T} h), coordinates reduced into [-m/2, m/2);
+// host arrays of m x d, either may be null.
+void points(const LatticePlan* p, int which, i64* keys, i64* sym);
+
 struct WaveLevel {
   Mat Ml, Nl;
   i64 ml = 0;
@@ -167,6 +173,13 @@ void upload_wave_plan(WavePlan* w);
 void free_wave_plan(WavePlan* w);
 // Dirichlet scaling mask of level l in natural G(M_l^T) order (Section 6.2)
 void dirichlet_mask(const WavePlan* w, int level, float* out);
+// Fiber maps of level l for the natural indices k0 .. k0+count-1 of
+// G(N_l^T), from the kernels' own index arithmetic: lifts[c*q + l] the
+// natural index in G(M_l^T) of the fiber member l; phase[c] (q = 2 only) the
+// residue rho with phi(h0) = exp(-2 pi i rho / m_l).  path 0: the kernels'
+// choice, 1: the 32-bit path (E_UNSUPPORTED if the level's bounds exclude
+// it), 2: the 64-bit path.
+void fiber_map(const WavePlan* w, int level, int path, i64 k0, i64 count, i64* lifts, i64* phase);
 // Scaling step of level l (Section 5.2, Theorem 3; P(J) cyclic): pattern
 // dimensions of M_l and N_l, the natural sample key in G(M_l) of the step's
 // direction N_l^{-1} z (z = J^{-1} g, g the first generating key of G(J) in

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_common.hpp"
+#include "fiber.hpp"
 #include "kernels.hpp"
 
 namespace lfft {
@@ -39,97 +40,20 @@ struct Fiber {
   float2 phi;         // phi(h0)
 };
 
-__device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
-  long long q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
-  return q;
-}
-
-template <class SD>
-__device__ __forceinline__ void reduce_hm(const SD& sd, long long* v) {
-  for (int i = sd.d - 1; i >= 0; --i) {
-    long long q = floordiv_ll(v[i], sd.HM[i][i]);
-    if (q)
-      for (int r = 0; r <= i; ++r) v[r] -= q * sd.HM[r][i];
-  }
-}
-
-__device__ __forceinline__ Fiber fiber_of(const SplitDesc& sd, long long klin) {
-  long long k[4] = {0, 0, 0, 0};
-  long long r = klin;
-  for (int i = sd.d - 1; i >= 0; --i) {
-    k[i] = r % sd.KN[i];
-    r /= sd.KN[i];
-  }
-  long long h0[4] = {k[0], k[1], k[2], k[3]};
-  reduce_hm(sd, h0);
-  long long h1[4] = {h0[0] + sd.s[0], h0[1] + sd.s[1], h0[2] + sd.s[2], h0[3] + sd.s[3]};
-  reduce_hm(sd, h1);
+__device__ __forceinline__ Fiber with_phase(const SplitDesc& sd, const fib::FiberIdx& x) {
   Fiber f;
-  f.i0 = 0;
-  f.i1 = 0;
-  long long rho = 0;
-  for (int i = 0; i < sd.d; ++i) {
-    f.i0 += h0[i] * sd.hstride[i];
-    f.i1 += h1[i] * sd.hstride[i];
-    rho = (rho + (h0[i] % sd.E) * (long long)sd.w[i]) % sd.E;
-  }
-  f.phi = sd.tw[rho];
+  f.i0 = x.i0;
+  f.i1 = x.i1;
+  f.phi = sd.tw[x.rho];
   return f;
-}
-
-// 32-bit fiber maps (sd.narrow): the same arithmetic with invariant-divisor
-// multiplications instead of 64-bit divisions.
-template <class SD>
-__device__ __forceinline__ void reduce_hm32(const SD& sd, int* v) {
-#pragma unroll
-  for (int i = 3; i >= 0; --i) {
-    if (i < sd.d) {
-      // floor(v / h) for |v| < 2^30 (bounded on the host)
-      const int h = sd.HM[i][i];
-      const int x = v[i];
-      const int q = x >= 0 ? (int)fast_div((unsigned)x, sd.fHM[i])
-                           : -(int)fast_div((unsigned)(h - 1 - x), sd.fHM[i]);
-#pragma unroll
-      for (int r = 0; r <= i; ++r) v[r] -= q * sd.HM[r][i];
-    }
-  }
 }
 
 __device__ __forceinline__ Fiber fiber_of32(const SplitDesc& sd, long long klin) {
-  int k[4] = {0, 0, 0, 0};
-  unsigned r = (unsigned)klin;
-#pragma unroll
-  for (int i = 3; i >= 0; --i) {
-    if (i < sd.d) {
-      const unsigned q = fast_div(r, sd.fKN[i]);
-      k[i] = (int)(r - q * (unsigned)sd.KN[i]);
-      r = q;
-    }
-  }
-  int h0[4] = {k[0], k[1], k[2], k[3]};
-  reduce_hm32(sd, h0);
-  int h1[4] = {h0[0] + sd.s[0], h0[1] + sd.s[1], h0[2] + sd.s[2], h0[3] + sd.s[3]};
-  reduce_hm32(sd, h1);
-  int i0 = 0, i1 = 0, acc = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (i < sd.d) {
-      i0 += h0[i] * (int)sd.hstride[i];
-      i1 += h1[i] * (int)sd.hstride[i];
-      acc += h0[i] * sd.w[i];
-    }
-  }
-  const unsigned q = fast_div((unsigned)acc, sd.fE);
-  Fiber f;
-  f.i0 = i0;
-  f.i1 = i1;
-  f.phi = sd.tw[(unsigned)acc - q * (unsigned)sd.E];
-  return f;
+  return with_phase(sd, fib::fiber_index32(sd, klin));
 }
 
 __device__ __forceinline__ Fiber fiber_at(const SplitDesc& sd, long long k) {
-  return sd.narrow ? fiber_of32(sd, k) : fiber_of(sd, k);
+  return with_phase(sd, sd.narrow ? fib::fiber_index32(sd, k) : fib::fiber_index64(sd, k));
 }
 
 __global__ void split_kernel(SplitDesc sd, long long batch, const float2* __restrict__ ah,
@@ -336,52 +260,7 @@ __global__ void __launch_bounds__(256) unsplit_chain_kernel(SplitChain c, long l
 // Q > 0 fixes q at compile time; Q = 0 reads it from the descriptor.
 template <int Q>
 __device__ __forceinline__ void fiber_q(const SplitQDesc& sd, long long klin, long long* idx) {
-  constexpr int QM = Q ? Q : kMaxQ;
-  const int q = Q ? Q : sd.q;
-  if (sd.narrow) {
-    int k[4] = {0, 0, 0, 0};
-    unsigned r = (unsigned)klin;
-#pragma unroll
-    for (int i = 3; i >= 0; --i) {
-      if (i < sd.d) {
-        const unsigned t = fast_div(r, sd.fKN[i]);
-        k[i] = (int)(r - t * (unsigned)sd.KN[i]);
-        r = t;
-      }
-    }
-    reduce_hm32(sd, k);
-#pragma unroll
-    for (int l = 0; l < QM; ++l) {
-      if (l < q) {
-        int h[4] = {k[0] + sd.s[l][0], k[1] + sd.s[l][1], k[2] + sd.s[l][2], k[3] + sd.s[l][3]};
-        if (l) reduce_hm32(sd, h);
-        int o = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < sd.d) o += h[i] * (int)sd.hstride[i];
-        idx[l] = o;
-      }
-    }
-  } else {
-    long long k[4] = {0, 0, 0, 0};
-    long long r = klin;
-    for (int i = sd.d - 1; i >= 0; --i) {
-      k[i] = r % sd.KN[i];
-      r /= sd.KN[i];
-    }
-    reduce_hm(sd, k);
-#pragma unroll
-    for (int l = 0; l < QM; ++l) {
-      if (l < q) {
-        long long h[4] = {k[0] + sd.s[l][0], k[1] + sd.s[l][1], k[2] + sd.s[l][2],
-                          k[3] + sd.s[l][3]};
-        if (l) reduce_hm(sd, h);
-        long long o = 0;
-        for (int i = 0; i < sd.d; ++i) o += h[i] * sd.hstride[i];
-        idx[l] = o;
-      }
-    }
-  }
+  fib::fiber_q_index<Q>(sd, klin, idx, sd.narrow != 0);
 }
 
 // u_l, sigma, v_0 and c of one fiber

@@ -13,7 +13,9 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblfft.so")
+# LFFT_LIBRARY: load another build of the same library (the sanitized host
+# build of the CPU tests); default: the in-tree build
+LIB_PATH = os.environ.get("LFFT_LIBRARY") or os.path.join(_HERE, "liblfft.so")
 
 LFFT_HOST_ONLY = 0x1
 LFFT_SPLIT_BF16 = 0x2
@@ -25,6 +27,8 @@ LFFT_MAP_SAMPLES = 0
 LFFT_MAP_FREQS = 1
 LFFT_MAP_SAMPLES_T = 2
 LFFT_MAP_FREQS_T = 3
+LFFT_POINTS_SAMPLES = 0
+LFFT_POINTS_FREQS = 1
 
 EXPORTS = [
     "lfft_plan_create", "lfft_plan_destroy", "lfft_plan_query", "lfft_plan_query_inverse_basis",
@@ -34,7 +38,8 @@ EXPORTS = [
     "lwt_decompose_backward", "lwt_reconstruct_backward", "lfft_trace_begin", "lfft_trace_end",
     "lfft_trace_get", "lfft_strerror", "lfft_batch_create", "lfft_batch_destroy",
     "lfft_batch_offsets", "lfft_batch_workspace_size", "lfft_batch_configure", "lfft_batch_config",
-    "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute",
+    "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute", "lfft_points",
+    "lwt_fiber_map", "lwt_coeff_layout",
 ]
 
 LFFT_BATCH_LOOP = 0
@@ -101,6 +106,10 @@ def lib():
             "lfft_batch_schedule": (ctypes.c_int, [_P, ctypes.c_int, _I32P, _I64P, _I64P, _I32P]),
             "lfft_batch_tune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _FP, _P]),
             "lfft_batch_execute": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
+            "lfft_points": (ctypes.c_int, [_P, ctypes.c_int, _I64P, _I64P]),
+            "lwt_fiber_map": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                             ctypes.c_int64, _I64P, _I64P]),
+            "lwt_coeff_layout": (ctypes.c_int, [_P, _I32P, _I32P, _I64P, _I64P, _I32P, _I32P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -196,6 +205,13 @@ class LatticePlan:
         _check(lib().lfft_index_map(self._h, int(which), _ptr64(out)), "lfft_index_map")
         return out
 
+    def points(self, which):
+        """(keys, sym_num) of lfft_points: int64 arrays (m, d) in natural order."""
+        keys = np.zeros((self.m, self.d), np.int64)
+        sym = np.zeros((self.m, self.d), np.int64)
+        _check(lib().lfft_points(self._h, int(which), _ptr64(keys), _ptr64(sym)), "lfft_points")
+        return keys, sym
+
     def workspace_bytes(self):
         return int(lib().lfft_workspace_size(self._h))
 
@@ -282,22 +298,39 @@ class WaveletPlan:
             self.level_m.append(ml.value)
             self.level_N.append(N)
         self.m = self.level_m[0]
-        # channels per level, q = |det J| (exact for the small J accepted)
-        self.q = int(round(abs(np.linalg.det(self.J.astype(np.float64)))))
+        q = ctypes.c_int()
+        nb = ctypes.c_int()
+        _check(lib().lwt_coeff_layout(self._h, ctypes.byref(q), ctypes.byref(nb), None, None, None,
+                                      None), "lwt_coeff_layout")
+        self.q = q.value
+        off = np.zeros(nb.value, np.int64)
+        ln = np.zeros(nb.value, np.int64)
+        lv = (ctypes.c_int * nb.value)()
+        ch = (ctypes.c_int * nb.value)()
+        _check(lib().lwt_coeff_layout(self._h, None, None, _ptr64(off), _ptr64(ln),
+                                      ctypes.cast(lv, _I32P), ctypes.cast(ch, _I32P)),
+               "lwt_coeff_layout")
+        self._blocks = [(int(lv[i]), int(ch[i]), int(off[i]), int(ln[i])) for i in range(nb.value)]
 
     def coeff_blocks(self):
-        """[(level, channel, offset, length)] of the coefficient blocks:
-        q = 2: [d2^(1) | .. | d2^(L) | d1^(L)] (channel 1 of every level,
-        then channel 0 of the last); q > 2: channels 1 .. q-1 of every
+        """[(level, channel, offset, length)] of the coefficient blocks of one
+        signal, as lwt_coeff_layout reports them: channels 1 .. q-1 of every
         level, then channel 0 of the last level."""
-        out, off = [], 0
-        for l, ml in enumerate(self.level_m):
-            n = ml // self.q
-            for j in range(1, self.q):
-                out.append((l, j, off, n))
-                off += n
-        out.append((self.levels - 1, 0, off, self.level_m[-1] // self.q))
-        return out
+        return list(self._blocks)
+
+    def fiber_map(self, level, path=0, k0=0, count=None):
+        """(lifts, phase) of lwt_fiber_map for the natural indices k0 ..
+        k0+count-1 of G(N_l^T): lifts int64 (count, q); phase int64 (count,)
+        for q = 2, None for q > 2."""
+        n = self.level_m[level] // self.q
+        if count is None:
+            count = n - k0
+        lifts = np.zeros((count, self.q), np.int64)
+        phase = np.zeros(count, np.int64) if self.q == 2 else None
+        _check(lib().lwt_fiber_map(self._h, int(level), int(path), int(k0), int(count),
+                                   _ptr64(lifts), _ptr64(phase) if phase is not None else None),
+               "lwt_fiber_map")
+        return lifts, phase
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -345,3 +345,146 @@ def test_split_bf16_plans():
     assert _err(lambda: lfft.LatticePlan(((1 << 13, 0), (0, 1 << 12)), host_only=True,
                                          split_bf16=True)) == -5
     assert _err(lambda: lfft.LatticePlan(((4, 0), (0, 4)), host_only=True, split_bf16=True)) == -5
+
+
+@pytest.mark.parametrize("M", MATS[:13] + [((997,),), ((-360,),)])
+def test_points_keys_and_symmetric_representatives(M):
+    """lfft_points: natural keys of both sides and their symmetric
+    representatives (times m), bit-exact against the oracle."""
+    from oracle import dft
+    p = lfft.LatticePlan(M, host_only=True)
+    if p.m > (1 << 20):
+        pytest.skip("oracle loop too slow at this size")
+    for which, side in ((lfft.LFFT_POINTS_SAMPLES, "samples"), (lfft.LFFT_POINTS_FREQS, "freqs")):
+        keys, sym = p.points(which)
+        ref_keys = dft.natural_keys(M, side)
+        assert np.array_equal(keys, ref_keys)
+        idx = np.random.default_rng(3).choice(p.m, size=min(p.m, 2000), replace=False)
+        for i in idx:
+            key = tuple(int(v) for v in ref_keys[i])
+            if side == "samples":
+                t, _ = L.symmetric_rep(M, key)
+            else:
+                _, t, _ = L.symmetric_rep_T(M, key)
+            assert tuple(int(v) for v in sym[i]) == t
+
+
+FIBER_CASES = [
+    (((32, 8), (-8, 32)), workloads.J_QUINCUNX, 3),
+    (((4096, 2048), (0, 4096)), workloads.J_QUINCUNX, 2),
+    (((16, 0), (0, 16)), workloads.J_D, 4),
+    (((12, 4), (0, 6)), workloads.J_X, 1),
+    (((12, 4), (0, 6)), workloads.J_Y, 1),
+    (((4, -3), (4, 5)), workloads.J_D, 1),
+    (((8, 0, 0), (0, 8, 4), (0, 0, 8)), ((2, 0, 0), (0, 1, 0), (0, 0, 1)), 2),
+    (((64,),), ((2,),), 3),
+]
+
+
+@pytest.mark.parametrize("M,J,levels", FIBER_CASES)
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_fiber_maps_q2(M, J, levels, path):
+    """lwt_fiber_map, q = 2: the lifts (natural lift h0 of k and its partner
+    h0 + s), the partner map of G(M_l^T) they imply, and the wavelet phase
+    residues, on both index paths of the kernels, bit-exact against the
+    oracle's fiber maps."""
+    w = lfft.WaveletPlan(M, J, levels, host_only=True)
+    for l, (Ml, Nl) in enumerate(W.level_matrices(M, J, levels)):
+        if w.level_m[l] > (1 << 21):
+            continue
+        lifts, phase = w.fiber_map(l, path=path)
+        _, i0, i1, rho, ml = W._fiber_maps(Ml, J)
+        assert np.array_equal(lifts[:, 0], i0)
+        assert np.array_equal(lifts[:, 1], i1)
+        assert np.array_equal(phase, rho)
+        # every class of G(M_l^T) is in exactly one fiber; partner is an involution
+        partner = np.full(ml, -1, np.int64)
+        partner[lifts[:, 0]] = lifts[:, 1]
+        partner[lifts[:, 1]] = lifts[:, 0]
+        assert np.array_equal(np.bincount(lifts.reshape(-1), minlength=ml), np.ones(ml))
+        assert np.array_equal(partner[partner], np.arange(ml))
+        # partner(h) = h + s reduced, for every natural h (independent of the lifts)
+        from oracle import dft
+        g0, _, _ = W.dilation_data(J)
+        s = np.array(L.matvec(L.transpose(Nl), g0), dtype=np.int64)
+        HMT, _ = L.hnf(L.transpose(Ml))
+        hk = dft.natural_keys(Ml, "freqs")
+        ref_partner = dft.box_index_np(HMT, dft.reduce_box_np(HMT, hk + s))
+        assert np.array_equal(partner, ref_partner)
+
+
+def test_fiber_map_wide_level():
+    """A level beyond the 32-bit bounds (m = 2^28): the kernels take the
+    64-bit path; sampled fibers against the oracle computed key by key."""
+    M, J = ((16384, 8192), (0, 16384)), workloads.J_QUINCUNX
+    w = lfft.WaveletPlan(M, J, 1, host_only=True)
+    with pytest.raises(lfft.LfftError) as e:
+        w.fiber_map(0, path=1, k0=0, count=4)
+    assert e.value.code == -5
+    Ml = L.as_matrix(M)
+    Nl = W.quotient(J, Ml)
+    g0, _, v = W.dilation_data(J)
+    s = L.matvec(L.transpose(Nl), g0)
+    HNT, _ = L.hnf(L.transpose(Nl))
+    HMT, _ = L.hnf(L.transpose(Ml))
+    n = w.level_m[0] // 2
+    rng = np.random.default_rng(11)
+    for k0 in [0, n - 64] + [int(x) for x in rng.integers(0, n - 64, 6)]:
+        lifts, phase = w.fiber_map(0, path=0, k0=k0, count=64)
+        lifts2, phase2 = w.fiber_map(0, path=2, k0=k0, count=64)
+        assert np.array_equal(lifts, lifts2) and np.array_equal(phase, phase2)
+        for c in range(64):
+            k, key = k0 + c, []
+            r = k
+            for i in range(len(M) - 1, -1, -1):
+                key.append(r % HNT[i][i])
+                r //= HNT[i][i]
+            key = key[::-1]
+            h0 = L.reduce_box(HMT, key)
+            h1 = L.reduce_box(HMT, [a + b for a, b in zip(h0, s)])
+            assert lifts[c, 0] == L.box_index(HMT, h0)
+            assert lifts[c, 1] == L.box_index(HMT, h1)
+            assert phase[c] == L.phase_residue(Ml, h0, v)
+
+
+@pytest.mark.parametrize("M,J,levels", [
+    (((16, 0), (0, 16)), ((2, 0), (0, 2)), 3),
+    (((7, 6), (2, 8)), ((2, 1), (0, 2)), 1),
+    (((18, 6), (-6, 12)), ((3, 0), (0, 1)), 1),
+    (((8, 0, 0), (0, 8, 4), (0, 0, 8)), ((2, 0, 0), (0, 2, 0), (0, 0, 2)), 2),
+    (((64,),), ((4,),), 3),
+])
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_fiber_maps_q(M, J, levels, path):
+    """lwt_fiber_map, q > 2: the q lifts of every fiber against the oracle's
+    q-channel fiber maps, on both index paths; no phase for q > 2."""
+    w = lfft.WaveletPlan(M, J, levels, host_only=True)
+    for l, (Ml, Nl) in enumerate(W.level_matrices(M, J, levels)):
+        lifts, phase = w.fiber_map(l, path=path)
+        assert phase is None
+        _, idx, ml = WQ.fiber_maps(Ml, J)
+        assert np.array_equal(lifts, idx.T)
+    with pytest.raises(lfft.LfftError):
+        lib = lfft.lib()
+        ph = np.zeros(1, np.int64)
+        lfft._check(lib.lwt_fiber_map(w._h, 0, 0, 0, 1, None, lfft._ptr64(ph)), "lwt_fiber_map")
+
+
+@pytest.mark.parametrize("M,J,levels", FIBER_CASES[:4] + [
+    (((16, 0), (0, 16)), ((2, 0), (0, 2)), 3), (((64,),), ((4,),), 3)])
+def test_coeff_layout(M, J, levels):
+    """lwt_coeff_layout: q and the blocks of the coefficient layout."""
+    w = lfft.WaveletPlan(M, J, levels, host_only=True)
+    q = abs(L.det(L.as_matrix(J)))
+    assert w.q == q
+    blocks = w.coeff_blocks()
+    mats = W.level_matrices(M, J, levels)
+    exp, off = [], 0
+    for l, (Ml, _) in enumerate(mats):
+        for j in range(1, q):
+            n = abs(L.det(Ml)) // q
+            exp.append((l, j, off, n))
+            off += n
+    exp.append((levels - 1, 0, off, abs(L.det(mats[-1][0])) // q))
+    assert blocks == exp
+    assert off + exp[-1][3] == abs(L.det(L.as_matrix(M)))

@@ -72,3 +72,37 @@ def test_gradients_finite_differences(M, J, levels):
     fd = (Lf(x, [a + h * b for a, b in zip(masks, u)]) - Lf(x, [a - h * b for a, b in zip(masks, u)])) / (2 * h)
     an = float(sum(np.sum(g * b) for g, b in zip(gm, u)))
     assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+def test_gradient_parts_finite_differences():
+    """The decomposition's and the reconstruction's contributions to the mask
+    gradient, each pinned by central differences that perturb only the masks
+    of that half; their sum is the whole mask gradient."""
+    M, J, levels = ((16, 8), (0, 16)), workloads.J_QUINCUNX, 2
+    m = abs(L.det(M))
+    rng = np.random.default_rng(8)
+    x = workloads.complex_normal(9, (2, m), np.complex128)
+    target = workloads.complex_normal(10, (2, m), np.complex128)
+    masks = [mk + 0.1 * rng.standard_normal(mk.shape) for mk in W.default_masks(M, J, levels)]
+    weights = [1.0] * levels
+    _, _, gd, gs = G.loss_and_grads(M, J, levels, x, masks, target, weights, parts=True)
+    _, _, gm = G.loss_and_grads(M, J, levels, x, masks, target, weights)
+    for a, b, c in zip(gd, gs, gm):
+        np.testing.assert_allclose(a + b, c, atol=1e-9 * np.abs(c).max())
+    pyr = G.TorchPyramid(M, J, levels)
+
+    def Lf(md, ms):
+        with torch.no_grad():
+            return float(G.pyramid_loss(pyr, torch.from_numpy(x), [torch.from_numpy(a) for a in md],
+                                        torch.from_numpy(target), weights,
+                                        masks_rec=[torch.from_numpy(a) for a in ms]))
+    u = [rng.standard_normal(mk.shape) for mk in masks]
+    h = 1e-5
+    plus = [a + h * b for a, b in zip(masks, u)]
+    minus = [a - h * b for a, b in zip(masks, u)]
+    fd_d = (Lf(plus, masks) - Lf(minus, masks)) / (2 * h)
+    fd_s = (Lf(masks, plus) - Lf(masks, minus)) / (2 * h)
+    an_d = float(sum(np.sum(g * b) for g, b in zip(gd, u)))
+    an_s = float(sum(np.sum(g * b) for g, b in zip(gs, u)))
+    assert abs(fd_d - an_d) <= 1e-6 * max(1.0, abs(an_d))
+    assert abs(fd_s - an_s) <= 1e-6 * max(1.0, abs(an_s))

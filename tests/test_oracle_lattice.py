@@ -158,3 +158,31 @@ def test_scaling_property_dimension(seed):
         M = L.matmul(J, N)
         dM, dN = L.pattern_dimension(M), L.pattern_dimension(N)
         assert dM in (dN, dN + 1)
+
+
+@pytest.mark.parametrize("M", [((4, -3), (4, 5)), ((3, 1), (-2, 4)), ((2, 0), (0, 4)),
+                               ((3, 1, 0), (0, 2, 1), (1, 0, 3)), ((5,),), ((6,),)])
+def test_symmetric_representatives_bruteforce(M):
+    """The symmetric representatives of the samples and of the frequencies are
+    the points of P(M) (resp. P(M^T)) moved into [-1/2, 1/2)^d, enumerated by
+    brute force (coordinates >= 1/2 shifted by -1), one per class."""
+    M = L.as_matrix(M)
+    for side, fn in (("samples", L.symmetric_rep), ("freqs", None)):
+        A = M if side == "samples" else L.transpose(M)
+        brute = set()
+        for y in L.lattice_points_bruteforce(A):
+            brute.add(tuple(c - 1 if c >= Fraction(1, 2) else c for c in y))
+        H, _ = L.hnf(A)
+        got = set()
+        Ainv = L.inverse(A)
+        for key in L.box_points(H):
+            if fn is not None:
+                t, m = fn(M, key)
+            else:
+                _, t, m = L.symmetric_rep_T(M, key)
+            pt = tuple(Fraction(x, m) for x in t)
+            assert all(Fraction(-1, 2) <= c < Fraction(1, 2) for c in pt)
+            y = L.matvec(Ainv, key)
+            assert all((a - b).denominator == 1 for a, b in zip(pt, y))
+            got.add(pt)
+        assert got == brute
