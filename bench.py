@@ -13,6 +13,10 @@ value = lattice-FFT GFLOP/s over the step: sum over every lattice FFT the
 step executes of 5 m_i log2 m_i, divided by the step time (the splits add
 time but no flops).  The forward FFT alone is reported beside it.
 
+Outside the timed regions the same outputs are compared with the FP64 oracle
+(max-abs and relative L2 error of every timed result), a plain device copy
+gives the practical bandwidth ceiling, and the oracle is timed on the host.
+
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
 import argparse
@@ -72,26 +76,68 @@ def load_traffic(kernel):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, m, levels):
-    """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: the forward lattice FFT and the 8-level decomposition of the
-    m = 2^24 signal (about half of one step)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """Cores this process may use, capped at the 16 of one GPU's host share."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _median_s(fn, reps=5):
+    fn()                                   # one warm-up run
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def cpu_baseline(cfg, m):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: the
+    forward lattice FFT of the m = 2^24 signal (Hermite row/column FFT with
+    scipy.fft), one warm-up then the median of 5 runs, with every host core
+    of the GPU's share and with one worker."""
     import numpy as np
     import workloads
-    from oracle import dft, wavelet
-    M, J = cfg["M"], cfg["J"]
+    from oracle import dft
+    M = cfg["M"]
     x = workloads.complex_normal(cfg["seed"], m).astype(np.complex128)
-    t0 = time.perf_counter()
-    dft.lattice_dft_hnf(M, x)
-    wavelet.decompose(x, M, J, levels)
-    dt = time.perf_counter() - t0
-    halves = [(m >> l) // 2 for l in range(levels)]
-    flops = 2 * fft_flops(m) + sum(fft_flops(h) for h in halves) + fft_flops(halves[-1])
-    return dict(value=round(flops / dt / 1e9, 4), unit="GFLOP/s", cores=os.cpu_count(),
-                kind="oracle",
-                sample="forward lattice FFT + 8-level decomposition of the m = 2^24 signal in "
-                       "float64 (Hermite row/column FFT, scipy.fft workers=%d): %.1f s"
-                       % (os.cpu_count(), dt))
+    cores = host_cores()
+    t_all = _median_s(lambda: dft.lattice_dft_hnf(M, x, workers=cores))
+    t_one = _median_s(lambda: dft.lattice_dft_hnf(M, x, workers=1))
+    f = fft_flops(m)
+    return dict(value=round(f / t_all / 1e9, 4), unit="GFLOP/s", cores=cores, kind="oracle",
+                cpu=cpu_model(),
+                sample="forward lattice FFT of the m = 2^24 signal in float64 (Hermite row/column "
+                       "FFT, scipy.fft workers=%d), median of 5 after one warm-up: %.3f s" % (cores, t_all),
+                workers_1={"value": round(f / t_one / 1e9, 4), "unit": "GFLOP/s",
+                           "seconds": round(t_one, 3)},
+                seconds=round(t_all, 3))
+
+
+def errors(got, ref):
+    """max-abs and relative L2 error of a GPU result against the FP64 oracle."""
+    import numpy as np
+    got = np.asarray(got).astype(np.complex128)
+    ref = np.asarray(ref)
+    return {"max_abs": float(np.max(np.abs(got - ref))),
+            "rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "ref_max_abs": float(np.max(np.abs(ref)))}
 
 
 def _time_ms(fn, reps, torch):
@@ -108,15 +154,17 @@ def _time_ms(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def variant_batched(torch, lfft, reps):
+def variant_batched(torch, lfft, reps, check):
     """512 lattices [[2^a, c], [0, 2^b]] (a + b in 10..18), concatenated
     complex64 signals: per-lattice launches vs the persistent launch vs its
     captured graph, after autotuning."""
+    import numpy as np
     import workloads
     seed = workloads.CONFIGS["batched"]["seed"]
     Ms = workloads.batched_matrices(seed=seed)
     plan = lfft.BatchPlan(Ms)
-    x = torch.from_numpy(workloads.complex_normal(seed, plan.total)).cuda()
+    xh = workloads.complex_normal(seed, plan.total)
+    x = torch.from_numpy(xh).cuda()
     y = torch.empty_like(x)
     t0 = time.perf_counter()
     plan.tune(x, reps=3, out=y)
@@ -129,20 +177,35 @@ def variant_batched(torch, lfft, reps):
         t = _time_ms(lambda: plan.execute(x, mode=mode, out=y), reps, torch)
         res[name] = {"ms": round(t, 4), "gflops": round(flops / (t / 1e3) / 1e9, 1),
                      "alg_gbs": round(16.0 * plan.total / (t / 1e3) / 1e9, 1)}
-    return {"workload": "512 lattices M=[[2^a,c],[0,2^b]], a+b uniform in 10..18, seed %d, "
-                        "sum m_i = %d complex64, forward FFT natural order" % (seed, plan.total),
-            "config": plan.config(), "tune_s": round(tune_s, 2), **res,
-            "graph_vs_loop": round(res["loop"]["ms"] / res["graph"]["ms"], 2)}
+    out = {"workload": "512 lattices M=[[2^a,c],[0,2^b]], a+b uniform in 10..18, seed %d, "
+                       "sum m_i = %d complex64, forward FFT natural order" % (seed, plan.total),
+           "config": plan.config(), "tune_s": round(tune_s, 2), **res,
+           "graph_vs_loop": round(res["loop"]["ms"] / res["graph"]["ms"], 2)}
+    if check:
+        # every 16th lattice of the graph-mode output against the oracle
+        from oracle import dft
+        plan.execute(x, mode=2, out=y)
+        yh = y.cpu().numpy()
+        got, ref = [], []
+        for i in range(0, len(Ms), 16):
+            ref.append(dft.lattice_dft_hnf(Ms[i], xh[off[i]:off[i + 1]].astype(np.complex128)[None, :],
+                                           workers=host_cores())[0])
+            got.append(yh[off[i]:off[i + 1]])
+        out["error_vs_oracle"] = dict(errors(np.concatenate(got), np.concatenate(ref)),
+                                      lattices=len(got))
+    return out
 
 
-def variant_split_bf16(torch, lfft, reps):
+def variant_split_bf16(torch, lfft, reps, check):
     """Precision workload: M = [[256, 64, 0], [0, 256, 64], [0, 0, 256]]
     (m = 2^24, eps = (64, 64, 4096)), forward FFT natural order: plain FP32
     butterflies vs radix-16 stages as split-BF16 MFMA products."""
+    import numpy as np
     import workloads
     cfg = workloads.CONFIGS["d3"]
     m = 1 << 24
-    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], m)).cuda()
+    xh = workloads.complex_normal(cfg["seed"], m)
+    x = torch.from_numpy(xh).cuda()
     pf = lfft.LatticePlan(cfg["M"])
     pb = lfft.LatticePlan(cfg["M"], split_bf16=True)
     yf = torch.empty_like(x)
@@ -154,22 +217,30 @@ def variant_split_bf16(torch, lfft, reps):
     for name, t in (("fp32", tf), ("split_bf16", tb)):
         res[name] = {"ms": round(t, 4), "gflops": round(fft_flops(m) / (t / 1e3) / 1e9, 1),
                      "alg_hbm_frac": round(16.0 * m / (t / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+    if check:
+        from oracle import dft
+        ref = dft.lattice_dft_hnf(cfg["M"], xh.astype(np.complex128), workers=host_cores())
+        res["fp32"]["error_vs_oracle"] = errors(yf.cpu().numpy(), ref)
+        res["split_bf16"]["error_vs_oracle"] = errors(yb.cpu().numpy(), ref)
     return {"workload": "d=3 M=[[256,64,0],[0,256,64],[0,0,256]] m=2^24 complex64 seed 3, "
                         "forward FFT natural order", **res,
             "rel_l2_bf16_vs_fp32": diff}
 
 
-def variant_grad(torch, lfft, reps):
+def variant_grad(torch, lfft, reps, check):
     """Differentiation workload: M = [[1024, 256], [0, 1024]] (m = 2^20),
     batch 16, 4 quincunx levels; loss = sum_l ||d2_l||^2 + ||S(D(x)) - t||^2;
     forward only vs forward + hand-written adjoint backward."""
+    import numpy as np
     import workloads
     from paper_1107_5415_amd import autograd as AG
     cfg = workloads.CONFIGS["grad"]
     B, m = cfg["batch"], 1 << 20
     plan = lfft.WaveletPlan(cfg["M"], cfg["J"], cfg["levels"], batch=B)
-    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], (B, m))).cuda().requires_grad_(True)
-    tgt = torch.from_numpy(workloads.complex_normal(cfg["target_seed"], (B, m))).cuda()
+    xh = workloads.complex_normal(cfg["seed"], (B, m))
+    th = workloads.complex_normal(cfg["target_seed"], (B, m))
+    x = torch.from_numpy(xh).cuda().requires_grad_(True)
+    tgt = torch.from_numpy(th).cuda()
     masks = [mk.requires_grad_(True) for mk in plan.dirichlet_masks(torch.device("cuda:0"))]
     blocks = AG.channel_blocks(plan)[:-1]
 
@@ -194,10 +265,21 @@ def variant_grad(torch, lfft, reps):
 
     tf = _time_ms(fwd, reps, torch)
     tb = _time_ms(fwd_bwd, reps, torch)
-    return {"workload": "M=[[1024,256],[0,1024]] m=2^20, batch 16, 4 quincunx levels, "
-                        "gradients wrt samples and the 4 FP32 masks",
-            "forward_ms": round(tf, 3), "forward_backward_ms": round(tb, 3),
-            "backward_over_forward": round((tb - tf) / tf, 2)}
+    out = {"workload": "M=[[1024,256],[0,1024]] m=2^20, batch 16, 4 quincunx levels, "
+                       "gradients wrt samples and the 4 FP32 masks",
+           "forward_ms": round(tf, 3), "forward_backward_ms": round(tb, 3),
+           "backward_over_forward": round((tb - tf) / tf, 2)}
+    if check:
+        from oracle import grad as G
+        fwd_bwd()
+        torch.cuda.synchronize()
+        _, rgx, rgm = G.loss_and_grads(cfg["M"], cfg["J"], cfg["levels"], xh.astype(np.complex128),
+                                       [mk.detach().cpu().numpy().astype(np.float64) for mk in masks],
+                                       th.astype(np.complex128), [1.0] * cfg["levels"])
+        out["error_vs_oracle"] = {
+            "grad_samples": errors(x.grad.cpu().numpy(), rgx),
+            "grad_masks": [errors(mk.grad.cpu().numpy(), r) for mk, r in zip(masks, rgm)]}
+    return out
 
 
 def variant_q4(torch, lfft, reps):
@@ -229,6 +311,34 @@ def variant_q4(torch, lfft, reps):
             **res}
 
 
+def aggregate(trace, steps):
+    """Per kernel: launches per step, ms per step, method and pass bytes."""
+    agg = {}
+    for name, b, pb, ms in trace:
+        a = agg.setdefault(name, [0.0, 0.0, 0.0, 0])
+        a[0] += ms
+        a[1] += b
+        a[2] += pb
+        a[3] += 1
+    return agg
+
+
+def kernel_table(agg, steps):
+    return {k: dict(launches=v[3] // steps, ms_per_step=round(v[0] / steps, 4),
+                    avg_launch_us=round(v[0] / v[3] * 1e3, 2),
+                    gbs=round(v[1] / (v[0] / 1e3) / 1e9, 1),
+                    pass_gbs=round(v[2] / (v[0] / 1e3) / 1e9, 1)) for k, v in agg.items()}
+
+
+def copy_ceiling(torch, x, y, reps=20):
+    """Achieved bandwidth of a plain device-to-device copy of the 128 MiB
+    signal (read + write), the practical ceiling of a streaming pass."""
+    t = _time_ms(lambda: y.copy_(x), reps, torch)
+    nbytes = 2.0 * x.numel() * x.element_size()
+    return {"bytes": nbytes, "ms": round(t, 4), "gbs": round(nbytes / (t / 1e3) / 1e9, 1),
+            "frac_of_peak": round(nbytes / (t / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +346,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the comparisons with the FP64 oracle")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the lattice FFT/wavelet hot path runs on a single "
@@ -255,13 +367,14 @@ def main():
     fplan = lfft.LatticePlan(M)
     wplan = lfft.WaveletPlan(M, J, levels)
     masks = wplan.dirichlet_masks(dev)
-    x = torch.from_numpy(workloads.complex_normal(cfg["seed"], m)).to(dev)
+    xh = workloads.complex_normal(cfg["seed"], m)
+    x = torch.from_numpy(xh).to(dev)
     X = torch.empty_like(x)
     Y = torch.empty_like(x)
     C = torch.empty_like(x)
     Rr = torch.empty_like(x)
 
-    def step(ev=None):
+    def step(ev=None, wp=wplan):
         if ev:
             ev[0].record()
         fplan.forward(x, out=X)
@@ -270,10 +383,10 @@ def main():
         fplan.inverse(X, out=Y)
         if ev:
             ev[2].record()
-        wplan.decompose(x, masks, out=C)
+        wp.decompose(x, masks, out=C)
         if ev:
             ev[3].record()
-        wplan.reconstruct(C, masks, out=Rr)
+        wp.reconstruct(C, masks, out=Rr)
         if ev:
             ev[4].record()
 
@@ -317,10 +430,20 @@ def main():
     torch.cuda.synchronize()
     trace = lfft.trace_end()
     ms_traced = sum(evs[k][0].elapsed_time(evs[k][4]) for k in range(args.steps)) / args.steps
-    # one plain device copy of 128 MiB outside the timed regions: the
-    # known-size reference against which profiler byte counters are scaled
-    Y.copy_(x)
+
+    # (3) and once more with a single-stream pyramid plan: every kernel runs
+    # alone on the GPU, so these are the isolated per-kernel durations (the
+    # default plan overlaps the large channel FFTs with the splits on a
+    # second stream, and kernels sharing the GPU take longer)
+    wplan1 = lfft.WaveletPlan(M, J, levels, single_stream=True)
+    step(wp=wplan1)
     torch.cuda.synchronize()
+    lfft.trace_begin(100000)
+    for k in range(args.steps):
+        step(wp=wplan1)
+    torch.cuda.synchronize()
+    trace1 = lfft.trace_end()
+    log("bench: traced passes done")
 
     phase = {}
     for i, name in enumerate(["fft_forward", "fft_inverse", "decompose", "reconstruct"]):
@@ -328,24 +451,30 @@ def main():
     flops = step_flops(m, levels)
     value = flops / (ms_step / 1e3) / 1e9
 
-    # dominant kernel: largest total time in the traced region
-    agg = {}
-    for name, b, ms in trace:
-        a = agg.setdefault(name, [0.0, 0.0, 0])
-        a[0] += ms
-        a[1] += b
-        a[2] += 1
+    # dominant kernel: largest total time in the traced region; `achieved` =
+    # its method bytes per launch (16 B per point per FFT, shared by the FFT's
+    # passes) over its average launch duration
+    agg = aggregate(trace, args.steps)
+    agg1 = aggregate(trace1, args.steps)
     dom = max(agg, key=lambda k: agg[k][0])
-    tot_ms, tot_b, cnt = agg[dom]
+    tot_ms, tot_b, tot_pb, cnt = agg[dom]
     achieved = tot_b / (tot_ms / 1e3) / 1e9
     traffic = load_traffic(dom)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic, kernel=dom,
                 launches_per_step=cnt // args.steps,
                 avg_launch_us=round(tot_ms / cnt * 1e3, 2),
-                alg_bytes_per_launch=tot_b / cnt)
-    kernels = {k: dict(launches=v[2] // args.steps, ms_per_step=round(v[0] / args.steps, 4),
-                       gbs=round(v[1] / (v[0] / 1e3) / 1e9, 1)) for k, v in agg.items()}
+                alg_bytes_per_launch=tot_b / cnt,
+                pass_bytes_per_launch=tot_pb / cnt,
+                pass_achieved=round(tot_pb / (tot_ms / 1e3) / 1e9, 1),
+                pass_frac=round(tot_pb / (tot_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4))
+    if dom in agg1:
+        i_ms, i_b, _, i_cnt = agg1[dom]
+        roof["isolated_avg_launch_us"] = round(i_ms / i_cnt * 1e3, 2)
+        roof["isolated_frac"] = round(i_b / (i_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
+    if traffic:
+        roof["traffic_gbs"] = round(traffic / (tot_ms / cnt / 1e3) / 1e9, 1)
+        roof["traffic_frac"] = round(roof["traffic_gbs"] / PEAK_HBM_GBS, 4)
 
     fwd_ms = fwd_alone_ms
     out = {
@@ -370,17 +499,40 @@ def main():
                         "alg_hbm_frac": round(16.0 * m / (fwd_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)},
         "phases_ms": {k: round(v, 4) for k, v in phase.items()},
         "traced_ms_per_step": round(ms_traced, 4),
-        "kernels": kernels,
+        "kernels": kernel_table(agg, args.steps),
+        "kernels_isolated": kernel_table(agg1, args.steps),
+        "copy_ceiling": copy_ceiling(torch, x, Y),
     }
+    del wplan1
+    if not args.no_check:
+        # every timed result of the step against the FP64 oracle (outside
+        # the timed regions; the oracle gets the complex64 inputs in float64)
+        log("bench: comparing with the FP64 oracle")
+        from oracle import dft, wavelet
+        cores = host_cores()
+        step()
+        torch.cuda.synchronize()
+        x64 = xh.astype(np.complex128)
+        Xh = X.cpu().numpy()
+        Ch = C.cpu().numpy()
+        acc = {"fft_forward": errors(Xh, dft.lattice_dft_hnf(M, x64, workers=cores)),
+               "fft_inverse": errors(Y.cpu().numpy(),
+                                     dft.lattice_dft_hnf(M, Xh.astype(np.complex128), inverse=True,
+                                                         workers=cores)),
+               "decompose": errors(Ch, wavelet.decompose(x64, M, J, levels)),
+               "reconstruct": errors(Rr.cpu().numpy(),
+                                     wavelet.reconstruct(Ch.astype(np.complex128), M, J, levels))}
+        out["error_vs_oracle"] = acc
     if not args.no_variants:
         log("bench: variants (split-BF16, batched, differentiation)")
-        out["variants"] = {"split_bf16": variant_split_bf16(torch, lfft, max(5, args.steps // 2)),
-                           "batched": variant_batched(torch, lfft, max(5, args.steps // 2)),
-                           "grad": variant_grad(torch, lfft, max(3, args.steps // 4)),
+        check = not args.no_check
+        out["variants"] = {"split_bf16": variant_split_bf16(torch, lfft, max(5, args.steps // 2), check),
+                           "batched": variant_batched(torch, lfft, max(5, args.steps // 2), check),
+                           "grad": variant_grad(torch, lfft, max(3, args.steps // 4), check),
                            "q4": variant_q4(torch, lfft, max(5, args.steps // 2))}
     if not args.no_cpu_baseline:
-        log("bench: timing the oracle on the host (one step)")
-        out["cpu_baseline"] = cpu_baseline(cfg, m, levels)
+        log("bench: timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(cfg, m)
     print(json.dumps(out), flush=True)
 
 

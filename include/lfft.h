@@ -74,6 +74,12 @@ extern "C" {
                                     Needs power-of-two elementary divisors
                                     and 32 <= m <= 2^24, else UNSUPPORTED    */
 
+#define LWT_SINGLE_STREAM 0x4u   /* lwt_plan_create only: run every kernel of
+                                    the pyramid on the caller's stream in issue
+                                    order (by default the channel FFTs of the
+                                    large levels run on a second, plan-owned
+                                    stream that overlaps the splits)         */
+
 /* ---- layouts (bitwise OR of one input and one output choice) ------------ */
 #define LFFT_IN_NATURAL 0x0u
 #define LFFT_IN_GRID 0x1u
@@ -166,7 +172,7 @@ int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, u
  * lwt_decompose / lwt_reconstruct with saved = NULL, and the two adjoints
  * without mask gradients (grad_masks = NULL).  Errors: ARG,
  * SINGULAR, NOT_INTEGRAL, OVERFLOW, UNSUPPORTED (q > 16, d > 4), NOMEM,
- * HIP. */
+ * HIP.  flags: 0, LFFT_HOST_ONLY, LWT_SINGLE_STREAM. */
 int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J, int levels,
                     int64_t batch, uint32_t flags);
 int lwt_plan_destroy(lwt_plan_t plan);
@@ -336,15 +342,20 @@ int lfft_batch_execute(lfft_batch_t plan, int inverse, int mode, const void* in,
 
 /* Start recording every kernel this library launches from now on (process
  * wide): two HIP events on the launch stream around each launch, the kernel
- * name and the algorithmic bytes of the launch (bytes the operation must move
- * at minimum: 16 per complex point of an FFT pass, 20 per point of a split
- * level).  capacity: maximum number of launches kept. */
+ * name and two byte counts of the launch.  Method bytes: the launch's share
+ * of the least the operation must move to or from HBM (a lattice FFT moves
+ * each complex point once in and once out, 16 B per point, and each of its np
+ * passes is credited 16 / np B per point; a split level 20 B per point, 4 of
+ * them the mask).  Pass bytes: the least the launch itself must move (16 B per
+ * point for every FFT pass; the method bytes for every other kernel).
+ * capacity: maximum number of launches kept. */
 int lfft_trace_begin(int capacity);
 /* Stop recording; *count receives the number of recorded launches. */
 int lfft_trace_end(int* count);
-/* Launch i of the last trace: kernel name (static string), algorithmic
- * bytes and duration in ms (waits for the launch to complete). */
-int lfft_trace_get(int i, const char** name, double* bytes, float* ms);
+/* Launch i of the last trace (host outputs, any may be NULL): kernel name
+ * (static string), method bytes, pass bytes and duration in ms (waits for the
+ * launch to complete). */
+int lfft_trace_get(int i, const char** name, double* bytes, double* pass_bytes, float* ms);
 
 /* Static description of a status code. */
 const char* lfft_strerror(int status);

@@ -162,12 +162,19 @@ void enqueue_persistent(BatchPlan* b, bool inverse, const void* in, void* out, v
     if (e != hipSuccess) throw StatusError{E_HIP};
     for (int ph = 0; ph < 2; ++ph) {
       if (D.phase_items[ph] == 0) continue;
-      double bytes = 0;
+      // method bytes: 16 B per point of every lattice with a pass in this
+      // phase, over its number of passes; pass bytes: 16 B per point
+      double bytes = 0, pass_bytes = 0;
       for (int i = 0; i < b->count; ++i) {
         const LatticePlan* p = b->tiled[i];
-        if (p && (int)p->fwd.passes.size() > ph) bytes += 16.0 * (double)b->m[i];
+        const int np = p ? (int)p->fwd.passes.size() : 0;
+        if (np > ph) {
+          bytes += 16.0 * (double)b->m[i] / np;
+          pass_bytes += 16.0 * (double)b->m[i];
+        }
       }
-      TraceScope ts(trace && trace_on() ? batch_kernel_name(b->tile_lg) : nullptr, bytes, s);
+      TraceScope ts(trace && trace_on() ? batch_kernel_name(b->tile_lg) : nullptr, bytes,
+                    pass_bytes, s);
       // never more workgroups than items: idle ones would only contend for
       // the queue heads
       const int grid = std::min(b->grid, std::max(8, D.phase_items[ph]));

@@ -154,7 +154,7 @@ int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J,
                     int64_t batch, uint32_t flags) {
   if (!plan) return LFFT_E_ARG;
   *plan = nullptr;
-  if (flags & ~LFFT_HOST_ONLY) return LFFT_E_ARG;
+  if (flags & ~(LFFT_HOST_ONLY | LWT_SINGLE_STREAM)) return LFFT_E_ARG;
   if (d > lfft::kMaxD) return LFFT_E_UNSUPPORTED;
   lfft::WavePlan* w = nullptr;
   int st = guarded([&] { w = lfft::build_wave_plan(d, M, J, levels, batch, flags); });

@@ -14,7 +14,7 @@ namespace lfft {
 namespace {
 struct Rec {
   const char* name;
-  double bytes;
+  double bytes, pass_bytes;
   hipEvent_t a, b;
 };
 struct State {
@@ -43,13 +43,14 @@ const char* kernel_name_intern(const char* fmt, ...) {
   return names.insert(buf).first->c_str();
 }
 
-int trace_begin(const char* kernel, double bytes, hipStream_t s) {
+int trace_begin(const char* kernel, double bytes, double pass_bytes, hipStream_t s) {
   State& S = st();
   std::lock_guard<std::mutex> g(S.mu);
   if (!S.on || S.used >= S.recs.size()) return -1;
   int i = (int)S.used++;
   S.recs[i].name = kernel;
   S.recs[i].bytes = bytes;
+  S.recs[i].pass_bytes = pass_bytes;
   if (hipEventRecord(S.recs[i].a, s) != hipSuccess) return -1;
   return i;
 }
@@ -90,13 +91,14 @@ int lfft_trace_end(int* count) {
   return LFFT_OK;
 }
 
-int lfft_trace_get(int i, const char** name, double* bytes, float* ms) {
+int lfft_trace_get(int i, const char** name, double* bytes, double* pass_bytes, float* ms) {
   using namespace lfft;
   State& S = st();
   std::lock_guard<std::mutex> g(S.mu);
   if (i < 0 || (size_t)i >= S.used) return LFFT_E_ARG;
   if (name) *name = S.recs[i].name;
   if (bytes) *bytes = S.recs[i].bytes;
+  if (pass_bytes) *pass_bytes = S.recs[i].pass_bytes;
   if (ms) {
     if (hipEventSynchronize(S.recs[i].b) != hipSuccess) return LFFT_E_HIP;
     if (hipEventElapsedTime(ms, S.recs[i].a, S.recs[i].b) != hipSuccess) return LFFT_E_HIP;

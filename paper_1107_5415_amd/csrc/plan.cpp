@@ -740,8 +740,8 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
       pd.out = out_grid ? E.out_grid : E.out_nat;
       pd.out.bstride = bout;
     }
-    TraceScope ts(trace_on() ? pass_kernel_name(pd) : nullptr,
-                  16.0 * (double)p->batch * (double)p->m, s);
+    const double fft_bytes = 16.0 * (double)p->batch * (double)p->m;
+    TraceScope ts(trace_on() ? pass_kernel_name(pd) : nullptr, fft_bytes / np, fft_bytes, s);
     hipError_t e = launch_pass(pd, src, dst, s);
     if (e != hipSuccess) throw StatusError{E_HIP};
   }
@@ -884,6 +884,8 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
     w->J = Mat::from(d, Jrm);
     w->levels = levels;
     w->batch = batch;
+    w->single_stream = (flags & kPlanSingleStream) != 0;
+    flags &= kPlanHostOnly;
     i64 DJ = det(w->J);
     if (DJ == 0) throw StatusError{E_SINGULAR};
     const i64 q = DJ < 0 ? -DJ : DJ;

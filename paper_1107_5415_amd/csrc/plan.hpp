@@ -26,6 +26,7 @@ enum Status : int {
 // plan flags (mirrors include/lfft.h)
 constexpr uint32_t kPlanHostOnly = 0x1;
 constexpr uint32_t kPlanSplitBf16 = 0x2;
+constexpr uint32_t kPlanSingleStream = 0x4;
 
 struct StatusError {
   int code;
@@ -164,6 +165,7 @@ struct WavePlan {
   size_t bd_elems = 0;          // BD region
   size_t fw2_elems = 0;         // FFT workspace of the second stream
   hipStream_t s2 = nullptr;
+  bool single_stream = false;   // LWT_SINGLE_STREAM: no second stream
   std::vector<hipEvent_t> ev;   // one per level
   hipEvent_t ev_join = nullptr;
 };

@@ -48,14 +48,20 @@ Bufs carve(const WavePlan* w, void* ws) {
   return b;
 }
 
-// s2 starts after everything enqueued on s so far (event e)
+// Stream of the large levels' channel FFTs: the plan's second stream, or
+// the caller's stream for a single-stream plan (everything in issue order).
+hipStream_t side_stream(const WavePlan* w, hipStream_t s) { return w->single_stream ? s : w->s2; }
+
+// the side stream starts after everything enqueued on s so far (event e)
 void fork(const WavePlan* w, hipEvent_t e, hipStream_t s) {
+  if (w->single_stream) return;
   check(hipEventRecord(e, s));
   check(hipStreamWaitEvent(w->s2, e, 0));
 }
 
-// s continues after everything enqueued on s2 so far
+// s continues after everything enqueued on the side stream so far
 void join(const WavePlan* w, hipStream_t s) {
+  if (w->single_stream) return;
   check(hipEventRecord(w->ev_join, w->s2));
   check(hipStreamWaitEvent(s, w->ev_join, 0));
 }
@@ -160,7 +166,7 @@ void decompose_runs(const WavePlan* w, const float2* x, const float* const* mask
       if (l == l0) fork(w, w->ev[l], s);
       forked = true;
       exec_lattice(w->lv[l].fftN, true, false, false, b.BD + w->big_d2[l],
-                   coeffs + coeff_offset(w, l), b.FW2, w->lv[l].ml / 2, m, w->s2);
+                   coeffs + coeff_offset(w, l), b.FW2, w->lv[l].ml / 2, m, side_stream(w, s));
     }
     cur = next;
   }
@@ -195,8 +201,8 @@ void reconstruct_runs(const WavePlan* w, const float2* coeffs, const float* cons
     for (int l = w->small_from - 1; l >= 0; --l) {
       const WaveLevel& V = w->lv[l];
       exec_lattice(V.fftN, false, false, false, coeffs + coeff_offset(w, l), b.BD + w->big_d2[l],
-                   b.FW2, m, V.ml / 2, w->s2);
-      check(hipEventRecord(w->ev[l], w->s2));
+                   b.FW2, m, V.ml / 2, side_stream(w, s));
+      check(hipEventRecord(w->ev[l], side_stream(w, s)));
     }
   }
   if (batched)
@@ -379,7 +385,7 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
       fork(w, w->ev[l], s);
       forked = true;
       exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW2, half, m,
-                   w->s2);
+                   side_stream(w, s));
     } else if (!batched) {
       exec_lattice(V.fftN, true, false, false, d2, coeffs + coeff_offset(w, l), b.FW, half, m, s);
     }

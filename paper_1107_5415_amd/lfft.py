@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("LFFT_LIBRARY") or os.path.join(_HERE, "liblfft.so")
 
 LFFT_HOST_ONLY = 0x1
 LFFT_SPLIT_BF16 = 0x2
+LWT_SINGLE_STREAM = 0x4
 LFFT_IN_NATURAL = 0x0
 LFFT_IN_GRID = 0x1
 LFFT_OUT_NATURAL = 0x0
@@ -95,6 +96,7 @@ def lib():
             "lfft_trace_begin": (ctypes.c_int, [ctypes.c_int]),
             "lfft_trace_end": (ctypes.c_int, [_I32P]),
             "lfft_trace_get": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                              ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double), _FP]),
             "lfft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "lfft_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, _I64P, ctypes.c_uint32]),
@@ -275,7 +277,7 @@ def inverse(x, M):
 class WaveletPlan:
     """Plan of the multi-level lattice wavelet pyramid (lwt_plan_*)."""
 
-    def __init__(self, M, J, levels, batch=1, host_only=False):
+    def __init__(self, M, J, levels, batch=1, host_only=False, single_stream=False):
         self.M = _mat(M)
         self.J = _mat(J)
         self.d = self.M.shape[0]
@@ -283,7 +285,9 @@ class WaveletPlan:
         self.batch = int(batch)
         h = _P()
         _check(lib().lwt_plan_create(ctypes.byref(h), self.d, _ptr64(self.M), _ptr64(self.J),
-                                     self.levels, self.batch, LFFT_HOST_ONLY if host_only else 0),
+                                     self.levels, self.batch,
+                                     (LFFT_HOST_ONLY if host_only else 0) |
+                                     (LWT_SINGLE_STREAM if single_stream else 0)),
                "lwt_plan_create")
         self._h = h
         self._ws = None
@@ -545,15 +549,16 @@ def trace_begin(capacity=100000):
 
 
 def trace_end():
-    """Stop timing and return [(kernel, algorithmic_bytes, ms), ...]."""
+    """Stop timing and return [(kernel, method_bytes, pass_bytes, ms), ...]."""
     n = ctypes.c_int()
     _check(lib().lfft_trace_end(ctypes.byref(n)), "lfft_trace_end")
     out = []
     for i in range(n.value):
         name = ctypes.c_char_p()
         b = ctypes.c_double()
+        pb = ctypes.c_double()
         ms = ctypes.c_float()
-        _check(lib().lfft_trace_get(i, ctypes.byref(name), ctypes.byref(b), ctypes.byref(ms)),
-               "lfft_trace_get")
-        out.append((name.value.decode(), b.value, ms.value))
+        _check(lib().lfft_trace_get(i, ctypes.byref(name), ctypes.byref(b), ctypes.byref(pb),
+                                    ctypes.byref(ms)), "lfft_trace_get")
+        out.append((name.value.decode(), b.value, pb.value, ms.value))
     return out

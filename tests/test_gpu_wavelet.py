@@ -202,3 +202,22 @@ def test_decompose_adjoint_dot_product():
     lhs = torch.vdot(Rv.flatten().to(torch.complex128), u.flatten().to(torch.complex128)).item()
     rhs = torch.vdot(v.flatten().to(torch.complex128), RHu.flatten().to(torch.complex128)).item()
     assert abs(lhs - rhs) / abs(lhs) < 1e-5
+
+
+def test_single_stream_plan_equals_default():
+    """A single-stream plan (LWT_SINGLE_STREAM) runs the same kernels on the
+    same data in issue order: coefficients and reconstruction bit-identical
+    to the default plan, which overlaps the large channel FFTs on a second
+    stream."""
+    from paper_1107_5415_amd import lfft
+    cfg = workloads.CONFIGS["large"]
+    M, J = cfg["M"], cfg["J"]
+    print("case single stream large", flush=True)
+    x = _dev(workloads.complex_normal(cfg["seed"], 1 << 24))
+    w2 = lfft.WaveletPlan(M, J, 8)
+    w1 = lfft.WaveletPlan(M, J, 8, single_stream=True)
+    masks = w2.dirichlet_masks("cuda")
+    c2 = w2.decompose(x, masks)
+    c1 = w1.decompose(x, masks)
+    assert torch.equal(c1, c2)
+    assert torch.equal(w1.reconstruct(c1, masks), w2.reconstruct(c2, masks))
