@@ -158,6 +158,20 @@ int lfft_forward(lfft_plan_t plan, const void* in, void* out, void* workspace, u
 int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, uint32_t layout,
                  hipStream_t stream);
 
+/* lfft_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument, and no allocation of any kind.  The intermediate
+ * grid between the passes lives in a fixed 64 MiB array of the library on
+ * every device that loads it (held until the process ends), so plans whose
+ * lfft_workspace_size() exceeds 64 MiB return UNSUPPORTED.  Every call on
+ * one device shares that array: calls that overlap in time on one device
+ * (different streams, different threads) race and must not be issued.  The
+ * first call on a device looks the array's address up once (no allocation).
+ * Same arguments otherwise as lfft_forward.  Errors: ARG, STATE,
+ * UNSUPPORTED, HIP. */
+int lfft_forward_noalloc(lfft_plan_t plan, const void* in, void* out, uint32_t layout,
+                         hipStream_t stream);
+
 /* ---- fast wavelet decomposition (Section 5.3) --------------------------- */
 
 /* Plan `levels` steps M_1 = M, N_l = J^{-1} M_l, M_{l+1} = N_l for a

@@ -5,18 +5,9 @@
 #include <new>
 
 #include "batch.hpp"
+#include "handles.hpp"
 #include "plan.hpp"
 #include "wave.hpp"
-
-struct lfft_plan_s {
-  lfft::LatticePlan* p;
-};
-struct lwt_plan_s {
-  lfft::WavePlan* w;
-};
-struct lfft_batch_s {
-  lfft::BatchPlan* b;
-};
 
 namespace {
 

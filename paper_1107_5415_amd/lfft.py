@@ -40,7 +40,7 @@ EXPORTS = [
     "lfft_trace_get", "lfft_strerror", "lfft_batch_create", "lfft_batch_destroy",
     "lfft_batch_offsets", "lfft_batch_workspace_size", "lfft_batch_configure", "lfft_batch_config",
     "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute", "lfft_points",
-    "lwt_fiber_map", "lwt_coeff_layout",
+    "lwt_fiber_map", "lwt_coeff_layout", "lfft_forward_noalloc",
 ]
 
 LFFT_BATCH_LOOP = 0
@@ -109,6 +109,7 @@ def lib():
             "lfft_batch_tune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _FP, _P]),
             "lfft_batch_execute": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
             "lfft_points": (ctypes.c_int, [_P, ctypes.c_int, _I64P, _I64P]),
+            "lfft_forward_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P]),
             "lwt_fiber_map": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                              ctypes.c_int64, _I64P, _I64P]),
             "lwt_coeff_layout": (ctypes.c_int, [_P, _I32P, _I32P, _I64P, _I64P, _I32P, _I32P]),
@@ -247,6 +248,18 @@ class LatticePlan:
 
     def inverse(self, x, out=None, layout=0):
         return self._run(lib().lfft_inverse, x, out, layout, "lfft_inverse")
+
+    def forward_noalloc(self, x, out, layout=0):
+        """lfft_forward_noalloc: the library allocates nothing; `out` must be
+        a preallocated complex64 device tensor like x."""
+        torch = _torch()
+        if not x.is_cuda or x.dtype != torch.complex64 or not x.is_contiguous():
+            raise RuntimeError("contiguous complex64 device tensor expected")
+        if x.numel() != self.batch * self.m or out.numel() != x.numel() or not out.is_contiguous():
+            raise RuntimeError("expected %d elements in and out" % (self.batch * self.m))
+        _check(lib().lfft_forward_noalloc(self._h, _dptr(x), _dptr(out), int(layout),
+                                          _stream_handle(x.device)), "lfft_forward_noalloc")
+        return out
 
 
 _plan_cache = {}
