@@ -25,6 +25,9 @@ Modules
            general q) with the Dirichlet mask of any q and a Householder
            completion of the wavelet channels, its pyramid, and the
            time-domain definition it must equal
+  interp   the change of basis between point values on P(M) and
+           coefficients in the orthonormal translates of the Dirichlet
+           kernel (Section 6.2), from the bracket sums of its coefficients
   scaling  the per-level scaling report of Theorem 3 (pattern dimensions,
            the step's direction) with brute-force pins
   grad     float64 torch autograd re-implementation for gradient checks
