@@ -80,6 +80,14 @@ extern "C" {
                                     large levels run on a second, plan-owned
                                     stream that overlaps the splits)         */
 
+#define LWT_SAMPLES 0x8u         /* lwt_plan_create only: the signal side of
+                                    the pyramid is point values on P(M), not
+                                    coefficients: lwt_decompose changes them
+                                    to the orthonormal translates of the
+                                    Dirichlet kernel first, lwt_reconstruct
+                                    returns point values (lfft_basis_change),
+                                    and the adjoints follow               */
+
 /* ---- layouts (bitwise OR of one input and one output choice) ------------ */
 #define LFFT_IN_NATURAL 0x0u
 #define LFFT_IN_GRID 0x1u
@@ -171,6 +179,33 @@ int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, u
  * UNSUPPORTED, HIP. */
 int lfft_forward_noalloc(lfft_plan_t plan, const void* in, void* out, uint32_t layout,
                          hipStream_t stream);
+
+/* ---- point values <-> orthonormal-translate coefficients --------------- */
+#define LFFT_SAMPLES_TO_COEFFS 0
+#define LFFT_COEFFS_TO_SAMPLES 1
+
+/* Change of basis in the space V_M of translates of the Dirichlet kernel
+ * phi_M (Section 6.2: the samples of a function are turned into its
+ * coefficients in the orthonormal translates T(y) phi_M before the wavelet
+ * decomposition).  Derived from eq. subspaces-coeffs: the point values
+ * s_x = g(2 pi x), x in P(M), of g = sum_y a_y T(y) phi_M are the cyclic
+ * convolution of a with phi_M's samples, so
+ *   (F(M) s)_h = sqrt(m) 2^{r(h)/2} (F(M) a)_h
+ * with r(h) the number of boundary hyperplanes of the cube M^T[-1/2,1/2]^d
+ * the class h lies on (the bracket sum of phi_M's coefficients).
+ * direction LFFT_SAMPLES_TO_COEFFS: in = s (NATURAL order of G(M)), out = a
+ * (same order), or out = F(M) a (NATURAL order of G(M^T)) if fourier != 0;
+ * LFFT_COEFFS_TO_SAMPLES: the inverse (in = a, or F(M) a if fourier != 0;
+ * out = s).  The bulk factor sqrt(m) is applied in the FFT's last pass, the
+ * 2^{-r/2} of the boundary classes by a kernel over those classes only
+ * (O(m^{(d-1)/d}) of them).  The first call builds the plan's table of
+ * boundary classes (one host scan of G(M^T) and one small device
+ * allocation).  workspace: lfft_basis_workspace_size() bytes.  Batch and
+ * layout as lfft_forward (NATURAL orders).  Errors: ARG, STATE, NOMEM,
+ * HIP. */
+size_t lfft_basis_workspace_size(lfft_plan_t plan);
+int lfft_basis_change(lfft_plan_t plan, int direction, int fourier, const void* in, void* out,
+                      void* workspace, hipStream_t stream);
 
 /* ---- fast wavelet decomposition (Section 5.3) --------------------------- */
 

@@ -40,6 +40,7 @@ import numpy as np
 
 from . import dft
 from . import lattice as L
+from . import wavelet as W
 
 
 def dirichlet_r(M):
@@ -47,12 +48,8 @@ def dirichlet_r(M):
     coordinates of M^{-T} h (symmetric representative, [-1/2, 1/2)) equal to
     -1/2 (Section 6.2)."""
     M = L.as_matrix(M)
-    hk = dft.natural_keys(M, "freqs")
-    out = np.zeros(hk.shape[0], dtype=np.int64)
-    for i, h in enumerate(hk):
-        _, t, m = L.symmetric_rep_T(M, tuple(int(v) for v in h))
-        out[i] = sum(1 for x in t if 2 * x == -m)
-    return out
+    t, m = W._sym_t(M, dft.natural_keys(M, "freqs"))
+    return np.sum(2 * t == -m, axis=1).astype(np.int64)
 
 
 def dirichlet_bracket_factor(M):

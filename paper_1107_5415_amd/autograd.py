@@ -40,6 +40,21 @@ class LatticeIFFT(torch.autograd.Function):
         return ctx.plan.forward(g.contiguous()), None
 
 
+class BasisChange(torch.autograd.Function):
+    """a = B s: point values on P(M) -> coefficients in the orthonormal
+    translates of the Dirichlet kernel (lfft_basis_change).  B = F^H W F with
+    a real diagonal W, so B is self-adjoint and its backward is B itself."""
+
+    @staticmethod
+    def forward(ctx, s, plan):
+        ctx.plan = plan
+        return plan.basis_change(s.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.basis_change(g.contiguous()), None
+
+
 class WaveletDecompose(torch.autograd.Function):
     """coeffs = D(x; masks) with the pyramid layout of lwt_decompose."""
 
@@ -88,6 +103,10 @@ def lattice_fft(x, M):
 
 def lattice_ifft(y, M):
     return LatticeIFFT.apply(y, get_plan(M, y.numel() // y.shape[-1]))
+
+
+def samples_to_coeffs(s, M):
+    return BasisChange.apply(s, get_plan(M, s.numel() // s.shape[-1]))
 
 
 def wavelet_decompose(x, plan, masks):

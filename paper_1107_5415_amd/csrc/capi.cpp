@@ -2,6 +2,7 @@
 // include/lfft.h).  Converts every internal error into a status code.
 #include "lfft.h"
 
+#include <cmath>
 #include <new>
 
 #include "batch.hpp"
@@ -141,11 +142,49 @@ int lfft_inverse(lfft_plan_t plan, const void* in, void* out, void* workspace, u
   return run_lattice(plan, true, in, out, workspace, layout, stream);
 }
 
+size_t lfft_basis_workspace_size(lfft_plan_t plan) {
+  if (!plan || !plan->p) return 0;
+  return (plan->p->ws_elems + (size_t)(plan->p->batch * plan->p->m)) * 8;
+}
+
+int lfft_basis_change(lfft_plan_t plan, int direction, int fourier, const void* in, void* out,
+                      void* workspace, hipStream_t stream) {
+  if (!plan || !plan->p || !in || !out || in == out || !workspace) return LFFT_E_ARG;
+  if (direction != LFFT_SAMPLES_TO_COEFFS && direction != LFFT_COEFFS_TO_SAMPLES) return LFFT_E_ARG;
+  lfft::LatticePlan* p = plan->p;
+  if (!device_ready(p)) return LFFT_E_STATE;
+  return guarded([&] {
+    lfft::build_boundary(p);
+    const long long bm = p->batch * p->m;
+    float2* fw = static_cast<float2*>(workspace);
+    float2* T = fw + p->ws_elems;
+    const float rsm = (float)(1.0 / std::sqrt((double)p->m));
+    const float sm = (float)std::sqrt((double)p->m);
+    if (direction == LFFT_SAMPLES_TO_COEFFS) {
+      // ahat = F(M) s / (sqrt(m) 2^{r/2}); a = F(M)^{-1} ahat
+      float2* dst = fourier ? static_cast<float2*>(out) : T;
+      lfft::exec_lattice(p, false, false, false, in, dst, fw, p->m, p->m, stream, rsm);
+      lfft::scale_boundary(p, -1, dst, p->batch, p->m, stream);
+      if (!fourier) lfft::exec_lattice(p, true, false, false, T, out, fw, p->m, p->m, stream);
+    } else {
+      // s = F(M)^{-1} (sqrt(m) 2^{r/2} ahat), ahat = F(M) a
+      if (fourier) {
+        if (hipMemcpyAsync(T, in, (size_t)bm * 8, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+          throw lfft::StatusError{LFFT_E_HIP};
+      } else {
+        lfft::exec_lattice(p, false, false, false, in, T, fw, p->m, p->m, stream);
+      }
+      lfft::scale_boundary(p, +1, T, p->batch, p->m, stream);
+      lfft::exec_lattice(p, true, false, false, T, out, fw, p->m, p->m, stream, sm);
+    }
+  });
+}
+
 int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J, int levels,
                     int64_t batch, uint32_t flags) {
   if (!plan) return LFFT_E_ARG;
   *plan = nullptr;
-  if (flags & ~(LFFT_HOST_ONLY | LWT_SINGLE_STREAM)) return LFFT_E_ARG;
+  if (flags & ~(LFFT_HOST_ONLY | LWT_SINGLE_STREAM | LWT_SAMPLES)) return LFFT_E_ARG;
   if (d > lfft::kMaxD) return LFFT_E_UNSUPPORTED;
   lfft::WavePlan* w = nullptr;
   int st = guarded([&] { w = lfft::build_wave_plan(d, M, J, levels, batch, flags); });

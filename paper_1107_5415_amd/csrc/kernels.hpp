@@ -73,4 +73,9 @@ hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2*
                             long long d0_bs, const float2* dw, long long dw_bs, const float* mask,
                             float2* ahat, long long ah_bs, hipStream_t s);
 
+// data[b * bstride + idx[i]] *= fac[r[i]] for every listed class i < n and
+// signal b < batch (the Dirichlet kernel's boundary classes, Section 6.2).
+hipError_t launch_boundary_scale(const long long* idx, const int* r, long long n, const float* fac,
+                                 float2* data, long long batch, long long bstride, hipStream_t s);
+
 }  // namespace lfft

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 #include "batch.hpp"
 #include "fiber.hpp"
@@ -652,7 +653,75 @@ void upload_plan(LatticePlan* p) {
 void free_plan(LatticePlan* p) {
   if (!p) return;
   if (p->dtab) (void)hipFree(p->dtab);
+  if (p->dbnd) (void)hipFree(p->dbnd);
   delete p;
+}
+
+void build_boundary(LatticePlan* p) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  if (p->bnd_built) return;
+  // r(h) = #{j : (sgn adj(M)^T h)_j = m/2 mod m}: only for even m
+  const int d = p->d;
+  const i64 m = p->m;
+  std::vector<i64> idx;
+  std::vector<int> rr;
+  if (m % 2 == 0) {
+    const Mat A = adjugate(p->M);
+    const i64 sg = det(p->M) < 0 ? -1 : 1;
+    const Mat& H = p->HMT;
+    std::vector<i64> v(d, 0);
+    for (i64 k = 0; k < m; ++k) {
+      i64 r = k;
+      for (int i = d - 1; i >= 0; --i) {
+        v[i] = r % H.a[i][i];
+        r /= H.a[i][i];
+      }
+      int cnt = 0;
+      for (int j = 0; j < d; ++j) {
+        i128 acc = 0;
+        for (int i = 0; i < d; ++i) acc += (i128)A.a[i][j] * v[i];
+        acc = (acc * sg) % m;
+        if (acc < 0) acc += m;
+        if (acc == m / 2) ++cnt;
+      }
+      if (cnt) {
+        idx.push_back(k);
+        rr.push_back(cnt);
+      }
+    }
+  }
+  void* dev = nullptr;
+  if (p->dtab && !idx.empty()) {
+    const size_t n = idx.size();
+    if (hipMalloc(&dev, n * (sizeof(i64) + sizeof(int))) != hipSuccess) throw StatusError{E_NOMEM};
+    if (hipMemcpy(dev, idx.data(), n * sizeof(i64), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(static_cast<char*>(dev) + n * sizeof(i64), rr.data(), n * sizeof(int),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(dev);
+      throw StatusError{E_HIP};
+    }
+  }
+  p->bnd_idx.swap(idx);
+  p->bnd_r.swap(rr);
+  p->dbnd = dev;
+  p->bnd_built = true;
+}
+
+void scale_boundary(const LatticePlan* p, int dir, void* data, long long batch, long long bstride,
+                    hipStream_t s) {
+  if (!p->bnd_built) throw StatusError{E_STATE};
+  const long long n = (long long)p->bnd_idx.size();
+  if (n == 0) return;
+  float fac[5];
+  for (int r = 0; r < 5; ++r) fac[r] = (float)std::pow(2.0, dir * 0.5 * r);
+  const i64* idx = static_cast<const i64*>(p->dbnd);
+  const int* rr = reinterpret_cast<const int*>(idx + n);
+  TraceScope ts(trace_on() ? "boundary_scale_kernel" : nullptr, 16.0 * (double)batch * (double)n,
+                s);
+  hipError_t e = launch_boundary_scale(reinterpret_cast<const long long*>(idx), rr, n, fac,
+                                       static_cast<float2*>(data), batch, bstride, s);
+  if (e != hipSuccess) throw StatusError{E_HIP};
 }
 
 void natural_to_grid(const LatticePlan* p, int which, i64* out) {
@@ -721,7 +790,8 @@ void points(const LatticePlan* p, int which, i64* keys, i64* sym) {
 }
 
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid, const void* in,
-                  void* out, void* ws, long long bin, long long bout, hipStream_t s) {
+                  void* out, void* ws, long long bin, long long bout, hipStream_t s,
+                  float scale_mul) {
   const Engine& E = !inverse ? p->fwd
                              : ((in_grid || out_grid) ? p->inv_grid
                                                       : (p->has_inv_rev ? p->inv_rev : p->inv_nat));
@@ -739,6 +809,7 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
     if (i == np - 1) {
       pd.out = out_grid ? E.out_grid : E.out_nat;
       pd.out.bstride = bout;
+      pd.scale *= scale_mul;
     }
     const double fft_bytes = 16.0 * (double)p->batch * (double)p->m;
     TraceScope ts(trace_on() ? pass_kernel_name(pd) : nullptr, fft_bytes / np, fft_bytes, s);
@@ -885,6 +956,7 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
     w->levels = levels;
     w->batch = batch;
     w->single_stream = (flags & kPlanSingleStream) != 0;
+    w->samples = (flags & kPlanSamples) != 0;
     flags &= kPlanHostOnly;
     i64 DJ = det(w->J);
     if (DJ == 0) throw StatusError{E_SINGULAR};
@@ -1104,6 +1176,7 @@ void build_channel_batches(WavePlan* w) {
 
 void upload_wave_plan(WavePlan* w) {
   upload_plan(w->fftM);
+  if (w->samples) build_boundary(w->fftM);
   for (auto& L : w->lv) {
     upload_plan(L.fftN);
     if (L.fftW) upload_plan(L.fftW);

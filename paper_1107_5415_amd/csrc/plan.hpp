@@ -27,6 +27,7 @@ enum Status : int {
 constexpr uint32_t kPlanHostOnly = 0x1;
 constexpr uint32_t kPlanSplitBf16 = 0x2;
 constexpr uint32_t kPlanSingleStream = 0x4;
+constexpr uint32_t kPlanSamples = 0x8;
 
 struct StatusError {
   int code;
@@ -100,6 +101,14 @@ struct LatticePlan {
   Blob blob;
   void* dtab = nullptr;     // device copy of blob
   size_t ws_elems = 0;      // workspace (complex64 elements) per call
+  // Classes h of G(M^T) on the boundary of the cube M^T [-1/2, 1/2]^d
+  // (r(h) > 0, Section 6.2), natural indices and r(h): the only frequencies
+  // where the Dirichlet kernel's bracket sum differs from m^{-1/2}.  Built on
+  // first use (build_boundary); dbnd holds [idx int64 x n][r int32 x n].
+  bool bnd_built = false;
+  std::vector<i64> bnd_idx;
+  std::vector<int> bnd_r;
+  void* dbnd = nullptr;
 };
 
 // tile_lg > 0 selects the fixed-tile schedule of the batched launch (tiles of
@@ -109,6 +118,9 @@ struct LatticePlan {
 LatticePlan* build_lattice_plan(int d, const i64* M, i64 batch, uint32_t flags, int tile_lg = 0,
                                 int order = 0);
 void upload_plan(LatticePlan* p);   // allocates device tables (throws StatusError)
+// The boundary classes of G(M^T) and their device copy (idempotent,
+// thread-safe; allocates on first call unless host-only).
+void build_boundary(LatticePlan* p);
 void free_plan(LatticePlan* p);
 
 // Natural -> grid index maps for tests (SAMPLES: lambda = Q^{-1} g mod eps,
@@ -166,6 +178,7 @@ struct WavePlan {
   size_t fw2_elems = 0;         // FFT workspace of the second stream
   hipStream_t s2 = nullptr;
   bool single_stream = false;   // LWT_SINGLE_STREAM: no second stream
+  bool samples = false;         // LWT_SAMPLES: point values on the signal side
   std::vector<hipEvent_t> ev;   // one per level
   hipEvent_t ev_join = nullptr;
 };
@@ -190,8 +203,14 @@ void fiber_map(const WavePlan* w, int level, int path, i64 k0, i64 count, i64* l
 void level_scaling(const WavePlan* w, int level, int& d_M, int& d_N, i64* key, i64* grid);
 
 // Execution (stream ordered).  bstride_in/out: batch strides in elements.
+// scale_mul multiplies the last pass's output scale.
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid,
                   const void* in, void* out, void* ws, long long bstride_in,
-                  long long bstride_out, hipStream_t s);
+                  long long bstride_out, hipStream_t s, float scale_mul = 1.0f);
+// Multiply the boundary classes of natural-frequency data [batch][bstride]
+// by pow(2, dir * r(h) / 2) (dir = -1: samples -> coefficients; +1: back),
+// on `s`; build_boundary must have run.
+void scale_boundary(const LatticePlan* p, int dir, void* data, long long batch,
+                    long long bstride, hipStream_t s);
 
 }  // namespace lfft

@@ -13,6 +13,8 @@
 //              level, [B][m_l/2] twice per level.
 #include "wave.hpp"
 
+#include <cmath>
+
 #include "batch.hpp"
 #include "kernels.hpp"
 #include "ktrace.hpp"
@@ -64,6 +66,31 @@ void join(const WavePlan* w, hipStream_t s) {
   if (w->single_stream) return;
   check(hipEventRecord(w->ev_join, w->s2));
   check(hipStreamWaitEvent(s, w->ev_join, 0));
+}
+
+// The top-level transforms between the signal and the Fourier data of the
+// pyramid.  With LWT_SAMPLES the signal holds point values, and the Fourier
+// data are those of the orthonormal-translate coefficients: a real diagonal
+// factor on G(M^T), (sqrt(m) 2^{r(h)/2})^basis with basis = -1 from samples
+// to coefficients and +1 back (the bracket sum of the Dirichlet kernel,
+// lfft_basis_change).  The bulk sqrt(m)^basis rides on the FFT's last pass,
+// the boundary classes are fixed up on the Fourier side.  basis = 0 (no
+// LWT_SAMPLES): the plain transforms.
+void top_forward(const WavePlan* w, const float2* x, float2* ahat, float2* fw, long long bin,
+                 long long bout, hipStream_t s, int basis) {
+  if (!w->samples) basis = 0;
+  const float f = basis ? (float)std::pow((double)w->m, 0.5 * basis) : 1.0f;
+  exec_lattice(w->fftM, false, false, false, x, ahat, fw, bin, bout, s, f);
+  if (basis) scale_boundary(w->fftM, basis, ahat, w->batch, bout, s);
+}
+
+// ahat is scaled in place when basis != 0
+void top_inverse(const WavePlan* w, float2* ahat, float2* x, float2* fw, long long bin,
+                 long long bout, hipStream_t s, int basis) {
+  if (!w->samples) basis = 0;
+  if (basis) scale_boundary(w->fftM, basis, ahat, w->batch, bin, s);
+  const float f = basis ? (float)std::pow((double)w->m, 0.5 * basis) : 1.0f;
+  exec_lattice(w->fftM, true, false, false, ahat, x, fw, bin, bout, s, f);
 }
 
 // algorithmic bytes of one split/unsplit level: read 8 B and write 8 B per
@@ -144,7 +171,7 @@ void decompose_runs(const WavePlan* w, const float2* x, const float* const* mask
   const int L = w->levels;
   const bool batched = w->chan_dec != nullptr;
   float2* cur = b.F0;
-  exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
+  top_forward(w, x, cur, b.FW, m, w->lv[0].ml, s, -1);
   bool forked = false;
   const auto runs = level_runs(w, b);
   for (const auto& r : runs) {
@@ -228,7 +255,7 @@ void reconstruct_runs(const WavePlan* w, const float2* coeffs, const float* cons
     }
     cur = next;
   }
-  exec_lattice(w->fftM, true, false, false, cur, x, b.FW, w->lv[0].ml, m, s);
+  top_inverse(w, cur, x, b.FW, w->lv[0].ml, m, s, +1);
 }
 }  // namespace
 
@@ -280,12 +307,12 @@ double split_q_bytes(long long B, long long ml) { return (16.0 * (double)B + 4.0
 float2* q_target(const QBufs& b, int l) { return l % 2 == 0 ? b.F0 : b.F1; }
 
 void decompose_q(const WavePlan* w, const float2* x, const float* const* masks, float2* coeffs,
-                 void* ws, hipStream_t s) {
+                 void* ws, hipStream_t s, int basis) {
   QBufs b = carve_q(w, ws);
   const long long B = w->batch, m = w->m, q = w->q;
   const int L = w->levels;
   const bool batched = w->chan_dec != nullptr;
-  exec_lattice(w->fftM, false, false, false, x, b.F0, b.FW, m, m, s);
+  top_forward(w, x, b.F0, b.FW, m, m, s, basis);
   float2* cur = b.F0;
   for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
@@ -315,7 +342,7 @@ void decompose_q(const WavePlan* w, const float2* x, const float* const* masks, 
 }
 
 void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* masks, float2* x,
-                   void* ws, hipStream_t s) {
+                   void* ws, hipStream_t s, int basis) {
   QBufs b = carve_q(w, ws);
   const long long B = w->batch, m = w->m, q = w->q;
   const int L = w->levels;
@@ -346,7 +373,7 @@ void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* 
     check(launch_unsplit_q(V.sq, B, cur, n, dw, (q - 1) * n, masks[l], next, V.ml, s));
     cur = next;
   }
-  exec_lattice(w->fftM, true, false, false, b.F0, x, b.FW, m, m, s);
+  top_inverse(w, b.F0, x, b.FW, m, m, s, basis);
 }
 }  // namespace
 
@@ -354,7 +381,7 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
                     float2* saved, void* ws, hipStream_t s) {
   if (w->q != 2) {
     if (saved) throw StatusError{E_UNSUPPORTED};
-    decompose_q(w, x, masks, coeffs, ws, s);
+    decompose_q(w, x, masks, coeffs, ws, s, -1);
     return;
   }
   if (!saved) {
@@ -368,7 +395,7 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
   const int L = w->levels;
   const bool batched = w->chan_dec != nullptr;
   float2* cur = saved;
-  exec_lattice(w->fftM, false, false, false, x, cur, b.FW, m, w->lv[0].ml, s);
+  top_forward(w, x, cur, b.FW, m, w->lv[0].ml, s, -1);
   long long soff = 0;
   bool forked = false;
   for (int l = 0; l < L; ++l) {
@@ -407,7 +434,7 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
                       float2* x, float2* saved, void* ws, hipStream_t s) {
   if (w->q != 2) {
     if (saved) throw StatusError{E_UNSUPPORTED};
-    reconstruct_q(w, coeffs, masks, x, ws, s);
+    reconstruct_q(w, coeffs, masks, x, ws, s, +1);
     return;
   }
   if (!saved) {
@@ -443,7 +470,7 @@ void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* cons
     }
     cur = next;
   }
-  exec_lattice(w->fftM, true, false, false, cur, x, b.FW, w->lv[0].ml, m, s);
+  top_inverse(w, cur, x, b.FW, w->lv[0].ml, m, s, +1);
 }
 
 void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* saved,
@@ -453,7 +480,7 @@ void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* 
     // the q-channel split's matrix is real, so the unsplit with the same
     // masks is its adjoint and the synthesis is the adjoint of the analysis
     if (gmasks) throw StatusError{E_UNSUPPORTED};
-    reconstruct_q(w, gc, masks, gx, ws, s);
+    reconstruct_q(w, gc, masks, gx, ws, s, -1);
     return;
   }
   Bufs b = carve(w, ws);
@@ -483,7 +510,9 @@ void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* 
     check(launch_unsplit(V.sd, B, g1, b.D2, half, masks[l], next, V.ml, s));
     g1 = next;
   }
-  exec_lattice(w->fftM, true, false, false, g1, gx, b.FW, w->lv[0].ml, m, s);
+  // adjoint of the top-level forward transform (with LWT_SAMPLES its real
+  // diagonal factor is its own adjoint)
+  top_inverse(w, g1, gx, b.FW, w->lv[0].ml, m, s, -1);
 }
 
 void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2* saved,
@@ -491,7 +520,7 @@ void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2
                                void* ws, hipStream_t s) {
   if (w->q != 2) {
     if (gmasks) throw StatusError{E_UNSUPPORTED};
-    decompose_q(w, gx, masks, gc, ws, s);
+    decompose_q(w, gx, masks, gc, ws, s, +1);
     return;
   }
   Bufs b = carve(w, ws);
@@ -507,7 +536,7 @@ void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2
   }
   // adjoint of the final inverse FFT is the forward FFT
   float2* g = b.F0;
-  exec_lattice(w->fftM, false, false, false, gx, g, b.FW, m, w->lv[0].ml, s);
+  top_forward(w, gx, g, b.FW, m, w->lv[0].ml, s, +1);
   for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
     const long long half = V.ml / 2;

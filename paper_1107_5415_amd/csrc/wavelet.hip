@@ -452,3 +452,36 @@ hipError_t launch_unsplit_chain(int K, const SplitChain& c, long long batch, con
 }
 
 }  // namespace lfft
+
+namespace lfft {
+namespace {
+struct Fac5 {
+  float f[5];
+};
+
+// One thread per boundary class, the batch loop inside.
+__global__ void __launch_bounds__(256) boundary_scale_kernel(const long long* __restrict__ idx,
+                                                             const int* __restrict__ r, long long n,
+                                                             Fac5 fac, float2* __restrict__ data,
+                                                             long long batch, long long bstride) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long k = idx[i];
+  const float f = fac.f[r[i]];
+  for (long long b = 0; b < batch; ++b) {
+    float2 v = data[b * bstride + k];
+    data[b * bstride + k] = make_float2(v.x * f, v.y * f);
+  }
+}
+}  // namespace
+
+hipError_t launch_boundary_scale(const long long* idx, const int* r, long long n, const float* fac,
+                                 float2* data, long long batch, long long bstride, hipStream_t s) {
+  Fac5 f;
+  for (int i = 0; i < 5; ++i) f.f[i] = fac[i];
+  hipLaunchKernelGGL(boundary_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx,
+                     r, n, f, data, batch, bstride);
+  return hipGetLastError();
+}
+
+}  // namespace lfft

@@ -20,6 +20,9 @@ LIB_PATH = os.environ.get("LFFT_LIBRARY") or os.path.join(_HERE, "liblfft.so")
 LFFT_HOST_ONLY = 0x1
 LFFT_SPLIT_BF16 = 0x2
 LWT_SINGLE_STREAM = 0x4
+LWT_SAMPLES = 0x8
+LFFT_SAMPLES_TO_COEFFS = 0
+LFFT_COEFFS_TO_SAMPLES = 1
 LFFT_IN_NATURAL = 0x0
 LFFT_IN_GRID = 0x1
 LFFT_OUT_NATURAL = 0x0
@@ -40,7 +43,8 @@ EXPORTS = [
     "lfft_trace_get", "lfft_strerror", "lfft_batch_create", "lfft_batch_destroy",
     "lfft_batch_offsets", "lfft_batch_workspace_size", "lfft_batch_configure", "lfft_batch_config",
     "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute", "lfft_points",
-    "lwt_fiber_map", "lwt_coeff_layout", "lfft_forward_noalloc",
+    "lwt_fiber_map", "lwt_coeff_layout", "lfft_forward_noalloc", "lfft_basis_workspace_size",
+    "lfft_basis_change",
 ]
 
 LFFT_BATCH_LOOP = 0
@@ -110,6 +114,8 @@ def lib():
             "lfft_batch_execute": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
             "lfft_points": (ctypes.c_int, [_P, ctypes.c_int, _I64P, _I64P]),
             "lfft_forward_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P]),
+            "lfft_basis_workspace_size": (ctypes.c_size_t, [_P]),
+            "lfft_basis_change": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
             "lwt_fiber_map": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                              ctypes.c_int64, _I64P, _I64P]),
             "lwt_coeff_layout": (ctypes.c_int, [_P, _I32P, _I32P, _I64P, _I64P, _I32P, _I32P]),
@@ -249,6 +255,25 @@ class LatticePlan:
     def inverse(self, x, out=None, layout=0):
         return self._run(lib().lfft_inverse, x, out, layout, "lfft_inverse")
 
+    def basis_change(self, x, direction=LFFT_SAMPLES_TO_COEFFS, fourier=False, out=None):
+        """lfft_basis_change: point values on P(M) <-> coefficients in the
+        orthonormal translates of the Dirichlet kernel (fourier=True: the
+        coefficient side is F(M) a in natural G(M^T) order)."""
+        torch = _torch()
+        if not x.is_cuda or x.dtype != torch.complex64:
+            raise RuntimeError("complex64 device tensor expected")
+        x = x.contiguous()
+        if x.numel() != self.batch * self.m:
+            raise RuntimeError("expected %d elements, got %d" % (self.batch * self.m, x.numel()))
+        if out is None:
+            out = torch.empty_like(x)
+        nb = int(lib().lfft_basis_workspace_size(self._h))
+        ws = torch.empty(max(nb // 8, 1), dtype=torch.complex64, device=x.device)
+        _check(lib().lfft_basis_change(self._h, int(direction), 1 if fourier else 0, _dptr(x),
+                                       _dptr(out), _dptr(ws), _stream_handle(x.device)),
+               "lfft_basis_change")
+        return out
+
     def forward_noalloc(self, x, out, layout=0):
         """lfft_forward_noalloc: the library allocates nothing; `out` must be
         a preallocated complex64 device tensor like x."""
@@ -290,7 +315,7 @@ def inverse(x, M):
 class WaveletPlan:
     """Plan of the multi-level lattice wavelet pyramid (lwt_plan_*)."""
 
-    def __init__(self, M, J, levels, batch=1, host_only=False, single_stream=False):
+    def __init__(self, M, J, levels, batch=1, host_only=False, single_stream=False, samples=False):
         self.M = _mat(M)
         self.J = _mat(J)
         self.d = self.M.shape[0]
@@ -300,7 +325,8 @@ class WaveletPlan:
         _check(lib().lwt_plan_create(ctypes.byref(h), self.d, _ptr64(self.M), _ptr64(self.J),
                                      self.levels, self.batch,
                                      (LFFT_HOST_ONLY if host_only else 0) |
-                                     (LWT_SINGLE_STREAM if single_stream else 0)),
+                                     (LWT_SINGLE_STREAM if single_stream else 0) |
+                                     (LWT_SAMPLES if samples else 0)),
                "lwt_plan_create")
         self._h = h
         self._ws = None
