@@ -56,8 +56,9 @@ extern "C" {
 #define LFFT_E_OVERFLOW (-4)     /* exact integer work would exceed int64     */
 #define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, mask
                                     gradients with |det J| > 2, or an
-                                    elementary divisor with a prime factor
-                                    that cannot be split to fit on chip      */
+                                    elementary divisor above 2^23 that cannot
+                                    be split into two factors of at most 8192
+                                    (shorter ones run as a chirp-z pass)     */
 #define LFFT_E_HIP (-6)          /* a HIP call or kernel launch failed        */
 #define LFFT_E_NOMEM (-7)        /* device table allocation failed            */
 #define LFFT_E_STATE (-8)        /* internal consistency check failed, or an
@@ -350,7 +351,9 @@ int lfft_batch_destroy(lfft_batch_t plan);
 /* offsets[count + 1]: element offset of every signal and the total (host). */
 int lfft_batch_offsets(lfft_batch_t plan, int64_t* offsets);
 
-/* Workspace bytes of lfft_batch_execute / lfft_batch_tune (8 * sum m_i). */
+/* Workspace bytes of lfft_batch_execute / lfft_batch_tune: 8 * sum m_i,
+ * plus one shared region for lattices with a chirp-z axis whose own plan
+ * needs more than their slot. */
 size_t lfft_batch_workspace_size(lfft_batch_t plan);
 
 /* Select a configuration: tiles of 2^tile_lg elements (11, 12 or 13) and

@@ -140,6 +140,13 @@ void build_dir(BatchPlan* b, bool inverse, BatchDir& D) {
   D.qbeg = reinterpret_cast<const int*>(static_cast<uint8_t*>(D.ditems) + items.size() * sizeof(int2));
 }
 
+// workspace of lattice i through its own plan: its slot, or the shared
+// region after the slots when its plan needs more (a chirp-z axis)
+float2* single_ws(const BatchPlan* b, const LatticePlan* p, int i, void* ws) {
+  float2* w = static_cast<float2*>(ws);
+  return p->ws_elems > (size_t)b->m[i] ? w + b->ws_elems : w + b->ws_off[i];
+}
+
 LatticePlan* single_plan(BatchPlan* b, int i) {
   if (!b->single[i]) {
     LatticePlan* p = build_lattice_plan(b->d, &b->Ms[(size_t)i * b->d * b->d], 1, 0);
@@ -190,8 +197,7 @@ void enqueue_persistent(BatchPlan* b, bool inverse, const void* in, void* out, v
     if (b->tiled[i]) continue;
     LatticePlan* p = single_plan(b, i);
     exec_lattice(p, inverse, false, false, static_cast<const float2*>(in) + b->in_off[i],
-                 static_cast<float2*>(out) + b->out_off[i], static_cast<float2*>(ws) + b->ws_off[i],
-                 p->m, p->m, s);
+                 static_cast<float2*>(out) + b->out_off[i], single_ws(b, p, i, ws), p->m, p->m, s);
   }
 }
 
@@ -243,6 +249,18 @@ BatchPlan* build_batch_plan_at(int count, int d, const i64* Ms, const i64* in_of
       b->ws_off = b->in_off;
       b->ws_elems = (size_t)b->total;
     }
+    // lattices whose own plan needs more workspace than their slot (a
+    // chirp-z axis; every elementary divisor a power of two never does)
+    for (int i = 0; i < count; ++i) {
+      const Smith S = smith(Mat::from(d, &b->Ms[(size_t)i * d * d]));
+      bool pow2 = true;
+      for (int j = 0; j < d; ++j) pow2 = pow2 && (S.eps[j] & (S.eps[j] - 1)) == 0;
+      if (pow2) continue;
+      LatticePlan* hp = build_lattice_plan(d, &b->Ms[(size_t)i * d * d], 1, kPlanHostOnly);
+      if (hp->ws_elems > (size_t)b->m[i]) b->extra_ws = std::max(b->extra_ws, hp->ws_elems);
+      free_plan(hp);
+    }
+    if (b->extra_ws && in_off) throw StatusError{E_UNSUPPORTED};
     if (!(flags & kPlanHostOnly)) {
       const size_t n = 16 * kHeadStride * sizeof(int);
       if (hipMalloc(&b->dheads, n) != hipSuccess) throw StatusError{E_NOMEM};
@@ -308,8 +326,8 @@ void exec_batch(BatchPlan* b, bool inverse, int mode, const void* in, void* out,
     for (int i = 0; i < b->count; ++i) {
       LatticePlan* p = single_plan(b, i);
       exec_lattice(p, inverse, false, false, static_cast<const float2*>(in) + b->in_off[i],
-                   static_cast<float2*>(out) + b->out_off[i],
-                   static_cast<float2*>(ws) + b->ws_off[i], p->m, p->m, s);
+                   static_cast<float2*>(out) + b->out_off[i], single_ws(b, p, i, ws), p->m, p->m,
+                   s);
     }
     return;
   }

@@ -44,6 +44,9 @@ struct BatchPlan {
   hipStream_t cap = nullptr;            // private stream for graph capture
   std::map<std::tuple<int, const void*, void*, void*>, hipGraphExec_t> graphs;
   size_t ws_elems = 0;
+  // lattices through their own plan whose workspace exceeds their slot (a
+  // chirp-z axis) share one region of extra_ws elements after ws_elems
+  size_t extra_ws = 0;
 };
 
 BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags);

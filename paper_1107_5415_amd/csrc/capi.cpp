@@ -371,7 +371,7 @@ int lfft_batch_offsets(lfft_batch_t plan, int64_t* offsets) {
 
 size_t lfft_batch_workspace_size(lfft_batch_t plan) {
   if (!plan) return 0;
-  return plan->b->ws_elems * 8;
+  return (plan->b->ws_elems + plan->b->extra_ws) * 8;
 }
 
 int lfft_batch_configure(lfft_batch_t plan, int tile_lg, int order) {

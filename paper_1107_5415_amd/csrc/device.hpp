@@ -43,7 +43,7 @@ struct StageDesc {
 
 struct PassDesc {
   int kind;                   // 0 generic, 1 register-resident power-of-two, 2 streaming,
-                              // 3 split-BF16 MFMA
+                              // 3 split-BF16 MFMA, 4 chirp-z (one whole axis)
   int P;                      // fast kernel: points per thread (16 or 32)
   int W;                      // fast kernel: pencils per workgroup
   int split;                  // fast kernel: exchange real and imaginary parts separately
@@ -65,6 +65,14 @@ struct PassDesc {
   int lo_n;
   const float2* tw_hi;
   const float2* tw_lo;
+  // chirp-z pass (kind 4): the axis of length L as a cyclic convolution of
+  // length bN (a power of two >= 2L - 1); chirp[j] = exp(-pi i j^2 / L),
+  // bhat = the DFT of the convolution kernel conj(chirp) (forward sign;
+  // both conjugated for sign +1); blue = index of the plan's inner FFT
+  int bN;
+  int blue;
+  const float2* chirp;
+  const float2* bhat;
   MapDesc in, out;
 };
 

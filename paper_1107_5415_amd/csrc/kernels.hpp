@@ -73,6 +73,14 @@ hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2*
                             long long d0_bs, const float2* dw, long long dw_bs, const float* mask,
                             float2* ahat, long long ah_bs, hipStream_t s);
 
+// Chirp-z pass (kind 4), three steps around the inner FFTs of length p.bN:
+// A[pen][j] = x(pen, j) chirp[j] for j < L, 0 up to bN (gather through p.in);
+// B[pen][k] *= bhat[k]; out(pen, k) = A[pen][k] chirp[k] scale (scatter
+// through p.out).  npen = batch * O * S pencils.
+hipError_t launch_blue_pre(const PassDesc& p, const float2* in, float2* A, hipStream_t s);
+hipError_t launch_blue_mul(const PassDesc& p, float2* B, hipStream_t s);
+hipError_t launch_blue_post(const PassDesc& p, const float2* A, float2* out, hipStream_t s);
+
 // data[b * bstride + idx[i]] *= fac[r[i]] for every listed class i < n and
 // signal b < batch (the Dirichlet kernel's boundary classes, Section 6.2).
 hipError_t launch_boundary_scale(const long long* idx, const int* r, long long n, const float* fac,

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -24,6 +25,7 @@ namespace lfft {
 namespace {
 constexpr i64 kMaxPencil = 8192;   // longest digit handled on chip
 constexpr i64 kMaxTile = 8192;     // elements of one single-pass tile
+constexpr i64 kMaxBlueAxis = i64(1) << 23;   // longest chirp-z axis (convolution <= 2^24)
 constexpr i64 kTileTarget = 4096;  // elements per tile for short pencils
 // pyramid levels whose channel (all signals) has at most this many points
 // run their channel FFTs in one batched launch
@@ -133,8 +135,63 @@ std::vector<int> pow2_radices(i64 n) {
   return r;
 }
 
+// Chirp-z tables of one axis of length n: chirp[j] = exp(-pi i (j^2 mod 2n) / n)
+// for j < n, and the plain DFT of the convolution kernel b (b_t = conj(chirp)
+// at t and at N - t for 0 <= t < n, zero elsewhere) over N points, both built
+// in FP64 and rounded once.
+struct BlueTables {
+  i64 N;
+  const float2* chirp;
+  const float2* bhat;
+};
+
+void fft_host(std::vector<std::complex<double>>& a) {
+  // iterative radix-2 decimation in time, exp(-2 pi i jk / N), N a power of two
+  const size_t N = a.size();
+  for (size_t i = 1, j = 0; i < N; ++i) {
+    size_t bit = N >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= N; len <<= 1) {
+    for (size_t i = 0; i < N; i += len)
+      for (size_t k = 0; k < len / 2; ++k) {
+        const double ang = -2.0 * M_PI * (double)k / (double)len;
+        const std::complex<double> w(std::cos(ang), std::sin(ang));
+        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+  }
+}
+
 struct TwCache {
   Blob* blob;
+  std::map<i64, BlueTables> blue;
+  BlueTables bluestein(i64 n) {
+    auto it = blue.find(n);
+    if (it != blue.end()) return it->second;
+    i64 N = 1;
+    while (N < 2 * n - 1) N *= 2;
+    std::vector<std::complex<double>> c(n), b(N, 0.0);
+    for (i64 j = 0; j < n; ++j) {
+      const i64 r = (i64)(((i128)j * j) % (2 * n));
+      const double a = -M_PI * (double)r / (double)n;
+      c[j] = std::complex<double>(std::cos(a), std::sin(a));
+    }
+    for (i64 t = 0; t < n; ++t) {
+      b[t] = std::conj(c[t]);
+      if (t) b[N - t] = std::conj(c[t]);
+    }
+    fft_host(b);
+    std::vector<float2> cf(n), bf(N);
+    for (i64 j = 0; j < n; ++j) cf[j] = make_float2((float)c[j].real(), (float)c[j].imag());
+    for (i64 k = 0; k < N; ++k) bf[k] = make_float2((float)b[k].real(), (float)b[k].imag());
+    BlueTables t{N, blob->ref(cf), blob->ref(bf)};
+    blue[n] = t;
+    return t;
+  }
   std::map<i64, const float2*> full;
   std::map<i64, std::pair<const float2*, const float2*>> two;
   const float2* table(i64 n) {
@@ -377,7 +434,18 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
         pd.kind = 2;
     }
     pd.nst = 0;
-    for (int g = R.a; g < R.b; ++g) {
+    if (R.b - R.a == 1 && dg[R.a].part == 3) {
+      // one whole axis by chirp-z: tables shared by every engine of the plan
+      pd.kind = 4;
+      int bi = 0;
+      for (int g = 0; g < R.a; ++g) bi += dg[g].part == 3 ? 1 : 0;
+      pd.blue = bi;
+      const BlueTables bt = tw.bluestein(dg[R.a].n);
+      pd.bN = (int)bt.N;
+      pd.chirp = bt.chirp;
+      pd.bhat = bt.bhat;
+    }
+    for (int g = R.a; g < R.b && pd.kind != 4; ++g) {
       int stride = (int)range_count(dg, g + 1, R.b);
       i64 Ns = 1;
       std::vector<int> rads = pd.kind == 1 ? pow2_radices(dg[g].n) : radices_of(dg[g].n);
@@ -453,6 +521,8 @@ void patch_engine(Engine& E, uintptr_t base) {
     for (int i = 0; i < pd.nst; ++i) patch(pd.st[i].tw, base);
     patch(pd.tw_hi, base);
     patch(pd.tw_lo, base);
+    patch(pd.chirp, base);
+    patch(pd.bhat, base);
     patch_map(pd.in, base);
     patch_map(pd.out, base);
   }
@@ -527,7 +597,12 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
               lo = c;
               break;
             }
-          if (!lo) throw StatusError{E_UNSUPPORTED};
+          if (!lo) {
+            // no split into two on-chip digits: the whole axis by chirp-z
+            if (n > kMaxBlueAxis) throw StatusError{E_UNSUPPORTED};
+            p->digits.push_back(Digit{j, n, 3, 1, 1});
+            continue;
+          }
           // power-of-two axes: a high digit of at least 32 points, so that
           // both passes run the register-resident kernels (2^15 = 32 x 1024
           // rather than 4 x 8192; 1.7-2.3 times faster on 2^14 .. 2^17
@@ -596,7 +671,18 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       }
     }
     p->ws_elems = p->ranges.size() > 1 ? (size_t)(p->m * batch) : 0;
-    TwCache tw{&p->blob, {}, {}};
+    // chirp-z axes: inner FFT plans and their share of the workspace
+    for (const auto& g : p->digits) {
+      if (g.part != 3) continue;
+      i64 N = 1;
+      while (N < 2 * g.n - 1) N *= 2;
+      const i64 pencils = batch * (p->m / g.n);
+      LatticePlan* in = build_lattice_plan(1, &N, pencils, flags & kPlanHostOnly);
+      p->blue.push_back(in);
+      p->blue_ws = std::max(p->blue_ws, (size_t)(2 * pencils * N) + in->ws_elems);
+    }
+    p->ws_elems += p->blue_ws;
+    TwCache tw{&p->blob, {}, {}, {}};
     Side fs = sample_side(p->Sf, p->M);
     Side ff = freq_side(p->Sf, p->M);
     Mat MT = transpose(p->M);
@@ -641,6 +727,7 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
 }
 
 void upload_plan(LatticePlan* p) {
+  for (LatticePlan* in : p->blue) upload_plan(in);
   if (p->dtab) return;
   p->dtab = upload_blob(p->blob);
   uintptr_t base = reinterpret_cast<uintptr_t>(p->dtab);
@@ -654,6 +741,7 @@ void free_plan(LatticePlan* p) {
   if (!p) return;
   if (p->dtab) (void)hipFree(p->dtab);
   if (p->dbnd) (void)hipFree(p->dbnd);
+  for (LatticePlan* in : p->blue) free_plan(in);
   delete p;
 }
 
@@ -789,6 +877,37 @@ void points(const LatticePlan* p, int which, i64* keys, i64* sym) {
   }
 }
 
+namespace {
+// One chirp-z pass: gather with the chirp into A (pencils x N), A -> B by the
+// inner forward FFT, B times the kernel's DFT, B -> A by the inner inverse
+// FFT, scatter with the chirp and the pass's scale.  The inner FFTs are
+// unitary, so bhat carries the plain DFT of the kernel: F^{-1}(F a . bhat)
+// is the cyclic convolution.  wb: 2 pencils N + the inner plan's workspace.
+void exec_chirp_z(const LatticePlan* p, const PassDesc& pd, const float2* src, float2* dst,
+                  float2* wb, hipStream_t s) {
+  const LatticePlan* in = p->blue[pd.blue];
+  const long long tot = in->batch * (long long)pd.bN;
+  float2* A = wb;
+  float2* B = wb + tot;
+  float2* iw = wb + 2 * tot;
+  const double by = 8.0 * (double)tot;
+  {
+    TraceScope ts(trace_on() ? "blue_pre_kernel" : nullptr, by + 8.0 * p->batch * p->m, s);
+    if (launch_blue_pre(pd, src, A, s) != hipSuccess) throw StatusError{E_HIP};
+  }
+  exec_lattice(in, false, false, false, A, B, iw, pd.bN, pd.bN, s);
+  {
+    TraceScope ts(trace_on() ? "blue_mul_kernel" : nullptr, 2.0 * by, s);
+    if (launch_blue_mul(pd, B, s) != hipSuccess) throw StatusError{E_HIP};
+  }
+  exec_lattice(in, true, false, false, B, A, iw, pd.bN, pd.bN, s);
+  {
+    TraceScope ts(trace_on() ? "blue_post_kernel" : nullptr, by + 8.0 * p->batch * p->m, s);
+    if (launch_blue_post(pd, A, dst, s) != hipSuccess) throw StatusError{E_HIP};
+  }
+}
+}  // namespace
+
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid, const void* in,
                   void* out, void* ws, long long bin, long long bout, hipStream_t s,
                   float scale_mul) {
@@ -812,6 +931,10 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
       pd.scale *= scale_mul;
     }
     const double fft_bytes = 16.0 * (double)p->batch * (double)p->m;
+    if (pd.kind == 4) {
+      exec_chirp_z(p, pd, src, dst, static_cast<float2*>(ws) + (np > 1 ? p->batch * p->m : 0), s);
+      continue;
+    }
     TraceScope ts(trace_on() ? pass_kernel_name(pd) : nullptr, fft_bytes / np, fft_bytes, s);
     hipError_t e = launch_pass(pd, src, dst, s);
     if (e != hipSuccess) throw StatusError{E_HIP};
@@ -984,7 +1107,7 @@ WavePlan* build_wave_plan(int d, const i64* Mrm, const i64* Jrm, int levels, i64
         gcls.push_back(g);
       }
     }
-    TwCache tw{&w->blob, {}, {}};
+    TwCache tw{&w->blob, {}, {}, {}};
     Mat Ml = w->M;
     for (int l = 0; l < levels; ++l) {
       WaveLevel L;

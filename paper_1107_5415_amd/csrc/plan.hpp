@@ -45,7 +45,8 @@ struct Side {
 struct Digit {
   int axis;                 // non-trivial grid axis
   i64 n;                    // digit length
-  int part;                 // 0 whole axis, 1 high digit, 2 low digit
+  int part;                 // 0 whole axis, 1 high digit, 2 low digit, 3 whole axis
+                            // by chirp-z (a prime factor too large for one pencil)
   i64 w_in;                 // grid-coordinate weight on the input side
   i64 w_out;                // grid-coordinate weight on the output side
 };
@@ -105,6 +106,10 @@ struct LatticePlan {
   // (r(h) > 0, Section 6.2), natural indices and r(h): the only frequencies
   // where the Dirichlet kernel's bracket sum differs from m^{-1/2}.  Built on
   // first use (build_boundary); dbnd holds [idx int64 x n][r int32 x n].
+  // chirp-z axes: the inner power-of-two FFT plan of each (batch = the
+  // axis's pencils), indexed by PassDesc::blue
+  std::vector<LatticePlan*> blue;
+  size_t blue_ws = 0;       // workspace of the chirp-z steps (after the pass buffer)
   bool bnd_built = false;
   std::vector<i64> bnd_idx;
   std::vector<int> bnd_r;

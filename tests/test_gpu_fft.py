@@ -67,6 +67,12 @@ CASES = [
     ("short_axis_2x8192_sheared", ((2, 1), (0, 8192)), 2),
     ("short_axis_16x2048", ((16, 0), (0, 2048)), 1),
     ("short_axes_d3", ((2, 0, 0), (0, 4, 0), (0, 0, 4096)), 2),
+    # a prime factor beyond one pencil (8209 > 8192): the axis by chirp-z
+    ("chirp_z_2x8209", ((1, 0), (0, 2 * 8209)), 2),
+    ("chirp_z_d1", ((2 * 8209,),), 1),
+    ("chirp_z_plus_axis_d3", ((2, 0, 0), (0, 2, 0), (0, 0, 8209)), 2),
+    ("chirp_z_sheared", ((8209, 1), (0, 3)), 1),
+    ("chirp_z_lower", ((8209, 0), (5, 8)), 1),
 ]
 
 
@@ -107,7 +113,8 @@ def _maps_from_oracle(M, q):
 
 
 @pytest.mark.parametrize("M", [((32, 8), (-8, 32)), ((128, 32), (0, 128)), ((2, 0), (0, 1 << 17)),
-                               ((3, 1, 0), (0, 3, 1), (1, 0, 3))])
+                               ((3, 1, 0), (0, 3, 1), (1, 0, 3)),
+                               ((2, 0, 0), (0, 2, 0), (0, 0, 8209))])
 def test_grid_layouts(M):
     """GRID order (Theorem 1, no rearrangement): every in/out layout pair."""
     lfft = _lfft()
@@ -183,3 +190,32 @@ def test_properties_at_any_size():
     back = plan.inverse(X)
     err = torch.linalg.vector_norm((back - x).to(torch.complex128)).item() / nx
     assert err < 2e-5
+
+
+def test_chirp_z_direct_bins():
+    """Chirp-z axis: exact direct-sum bins of the natural output."""
+    lfft = _lfft()
+    M = ((2, 0, 0), (0, 2, 0), (0, 0, 8209))
+    m = abs(L.det(M))
+    x = workloads.complex_normal(13, m)
+    X = lfft.LatticePlan(M).forward(_dev(x)).cpu().numpy()
+    rng = np.random.default_rng(3)
+    hk = dft.natural_keys(M, "freqs")
+    idx = rng.choice(m, 24, replace=False)
+    bins = dft.direct_bins(M, x.astype(np.complex128), [tuple(int(v) for v in hk[i]) for i in idx])
+    assert rel_l2(X[idx], bins) < TOL
+
+
+def test_chirp_z_in_batch():
+    """A batch mixing power-of-two lattices with chirp-z ones: the chirp-z
+    lattices run through their own plans in the shared extra workspace."""
+    lfft = _lfft()
+    Ms = [((1, 0), (0, 2 * 8209)), ((64, 16), (0, 256)), ((8209, 1), (0, 3)), ((32, 8), (-8, 32))]
+    plan = lfft.BatchPlan(Ms)
+    x = workloads.complex_normal(14, plan.total)
+    for mode in (0, 1, 2):
+        y = plan.execute(_dev(x), mode=mode).cpu().numpy()
+        off = plan.offsets
+        for i, M in enumerate(Ms):
+            ref = oracle_fft(M, x[off[i]:off[i + 1]][None, :])[0]
+            assert rel_l2(y[off[i]:off[i + 1]], ref) < TOL, (mode, i)

@@ -255,8 +255,8 @@ def test_error_codes():
     assert _err(lambda: lfft.WaveletPlan([[8, 0], [0, 8]], [[1, 0], [0, 1]], 1, host_only=True)) == -5
     # integral first level, non-integral later level
     assert _err(lambda: lfft.WaveletPlan([[4, 0], [0, 2]], workloads.J_X, 3, host_only=True)) == -3
-    # a large prime cycle cannot be split to fit on chip
-    assert _err(lambda: lfft.LatticePlan([[1, 0], [0, 8209 * 2]], host_only=True)) == -5
+    # a prime cycle longer than the chirp-z bound (2^23)
+    assert _err(lambda: lfft.LatticePlan([[1, 0], [0, 8388617]], host_only=True)) == -5
     # execute on a host-only plan
     p = lfft.LatticePlan([[4, 0], [0, 4]], host_only=True)
     lib = lfft.lib()
@@ -488,3 +488,19 @@ def test_coeff_layout(M, J, levels):
     exp.append((levels - 1, 0, off, abs(L.det(mats[-1][0])) // q))
     assert blocks == exp
     assert off + exp[-1][3] == abs(L.det(L.as_matrix(M)))
+
+
+@pytest.mark.parametrize("M,eps,passes", [
+    (((1, 0), (0, 2 * 8209)), (1, 16418), 1),
+    (((2 * 8209,),), (16418,), 1),
+    (((2, 0, 0), (0, 2, 0), (0, 0, 8209)), (1, 2, 16418), 2),
+    (((8209, 1), (0, 3)), (1, 24627), 1),
+    (((8209, 0), (5, 8)), (1, 65672), 1),
+])
+def test_chirp_z_axes_plan(M, eps, passes):
+    """Cycles with a prime factor beyond one pencil (8209 > 8192) plan a
+    chirp-z pass for their axis instead of failing."""
+    p = lfft.LatticePlan(M, host_only=True)
+    q = p.query()
+    assert tuple(int(e) for e in q["eps"]) == eps
+    assert q["passes"] == passes
