@@ -4,6 +4,12 @@
       [--trace TRACE_CSV --tail-kernel NAME --tail-n N]
       per-kernel calls / total / average duration from --kernel-trace --stats,
       and the average of the last N dispatches of one kernel
+  python -m paper_1107_5415_amd.profsum sq CSV [CSV ...] --write-csv WRITE_CSV --copy-kib KIB
+      --cmd "..." [--cmd "..."] --out FILE
+      per-kernel averages per dispatch of the SQ counters in the CSVs, with
+      VALU lane-operations per complex point (SQ_INSTS_VALU * 64 / points,
+      points = output bytes / 8 from the calibrated WRITE_SIZE run) and the
+      ratio of wait to VALU instructions
   python -m paper_1107_5415_amd.profsum traffic FETCH_CSV WRITE_CSV --kernel NAME
       --copy-kib KIB --alg-bytes B --sources F1,F2 --cmd-fetch "..." --cmd-write "..."
       --out JSON [--alg-per-write R]
@@ -138,6 +144,41 @@ def traffic(fetch_csv, write_csv, kernel, copy_kib, alg_bytes, sources, cmd_f, c
     print(json.dumps(data[kernel]))
 
 
+def sq(csvs, write_csv, copy_kib, cmds, out):
+    vals = {}
+    for path in csvs:
+        per = {}
+        for r in csv.DictReader(open(path)):
+            key = (_short(r["Kernel_Name"]), r["Counter_Name"])
+            per.setdefault(key, {}).setdefault(r["Dispatch_Id"], 0.0)
+            per[key][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        for (k, c), d in per.items():
+            vals.setdefault(k, {})[c] = statistics.mean(d.values())
+    wr = _per_dispatch(write_csv, "WRITE_SIZE")
+    cw = max(v for k, l in wr.items() if COPY_KERNEL in k for v in l)
+    scale = copy_kib / cw
+    points = {}
+    for k, l in wr.items():
+        points[_short(k)] = statistics.mean(l) * scale * 1024 / 8
+    cols = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_INSTS_SALU",
+            "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"]
+    lines = ["# rocprofv3 --pmc SQ counters, averages per dispatch over the run (all launches of each kernel)"]
+    lines += ["# command: " + c for c in cmds]
+    lines += ["# lane_ops_per_point = SQ_INSTS_VALU * 64 / points; points = WRITE_SIZE bytes / 8 per dispatch "
+              "(calibrated on the run's largest device copy); wait/valu = SQ_WAIT_INST_ANY / SQ_INSTS_VALU", ""]
+    lines.append("%-56s" % "kernel" + "".join("%16s" % c.replace("SQ_", "") for c in cols) +
+                 "%12s%10s" % ("ops/point", "wait/valu"))
+    order = sorted(vals, key=lambda k: -vals[k].get("SQ_WAVE_CYCLES", 0))
+    for k in order:
+        v = vals[k]
+        pts = points.get(k)
+        ops = v.get("SQ_INSTS_VALU", 0) * 64 / pts if pts else float("nan")
+        wv = v.get("SQ_WAIT_INST_ANY", 0) / v["SQ_INSTS_VALU"] if v.get("SQ_INSTS_VALU") else float("nan")
+        lines.append("%-56s" % k[:56] + "".join("%16.1f" % v.get(c, float("nan")) for c in cols) +
+                     "%12.1f%10.2f" % (ops, wv))
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what")
@@ -148,6 +189,12 @@ def main():
     s.add_argument("--trace", default=None)
     s.add_argument("--tail-kernel", default=None)
     s.add_argument("--tail-n", type=int, default=0)
+    q = sub.add_parser("sq")
+    q.add_argument("csvs", nargs="+")
+    q.add_argument("--write-csv", required=True)
+    q.add_argument("--copy-kib", type=float, required=True)
+    q.add_argument("--cmd", action="append", required=True)
+    q.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -162,6 +209,8 @@ def main():
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.csv, a.cmd, a.out, a.trace, a.tail_kernel, a.tail_n)
+    elif a.what == "sq":
+        sq(a.csvs, a.write_csv, a.copy_kib, a.cmd, a.out)
     elif a.what == "traffic":
         traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_kib, a.alg_bytes, a.sources.split(","),
                 a.cmd_fetch, a.cmd_write, a.out, a.alg_per_write)
