@@ -626,7 +626,10 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
         P *= p->digits[k].n;
         ++k;
       }
-      if (k >= 1 && k < p->digits.size() && p->digits[k].part == 0 && is_pow2(P)) {
+      // (not beyond the streaming kernels' 2^28 bound, like the long-cycle
+      // split above: unmeasured there)
+      if (k >= 1 && k < p->digits.size() && p->digits[k].part == 0 && is_pow2(P) &&
+          p->m < (i64(1) << 28)) {
         const Digit g = p->digits[k];
         if (is_pow2(g.n) && P * g.n > kMaxPencil) {
           const i64 hi = 32 / P, lo = g.n / hi;

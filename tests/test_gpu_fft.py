@@ -67,6 +67,9 @@ CASES = [
     ("short_axis_2x8192_sheared", ((2, 1), (0, 8192)), 2),
     ("short_axis_16x2048", ((16, 0), (0, 2048)), 1),
     ("short_axes_d3", ((2, 0, 0), (0, 4, 0), (0, 0, 4096)), 2),
+    # the short axis's split axis followed by another axis (three passes)
+    ("short_axis_split_then_axis", ((16, 0, 0), (0, 1024, 0), (0, 0, 1024)), 1),
+    ("short_axis_split_then_axis_sheared", ((16, 16, 0), (0, 1024, 1024), (0, 0, 1024)), 1),
     # a prime factor beyond one pencil (8209 > 8192): the axis by chirp-z
     ("chirp_z_2x8209", ((1, 0), (0, 2 * 8209)), 2),
     ("chirp_z_d1", ((2 * 8209,),), 1),

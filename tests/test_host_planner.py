@@ -504,3 +504,14 @@ def test_chirp_z_axes_plan(M, eps, passes):
     q = p.query()
     assert tuple(int(e) for e in q["eps"]) == eps
     assert q["passes"] == passes
+
+
+def test_short_axis_split_bounds():
+    """A short leading axis takes the high digit of the next axis below
+    2^28 points (three passes for (16, 1024, 1024)); at 2^28 the split is not
+    taken (the two whole axes of 4096 and the short one)."""
+    p = lfft.LatticePlan(((16, 0, 0), (0, 1024, 0), (0, 0, 1024)), host_only=True)
+    assert p.query()["passes"] == 3
+    q = lfft.LatticePlan(((16, 0, 0), (0, 4096, 0), (0, 0, 4096)), host_only=True).query()
+    assert tuple(int(e) for e in q["eps"]) == (16, 4096, 4096)
+    assert q["passes"] == 3
