@@ -63,6 +63,8 @@ extern "C" {
 #define LFFT_E_NOMEM (-7)        /* device table allocation failed            */
 #define LFFT_E_STATE (-8)        /* internal consistency check failed, or an
                                     execute call on a host-only plan          */
+#define LFFT_E_IO (-9)           /* a file could not be read or written, or is
+                                    not a tuning cache                        */
 
 /* ---- plan flags --------------------------------------------------------- */
 #define LFFT_HOST_ONLY 0x1u      /* integer planning only: no device tables,
@@ -377,11 +379,39 @@ int lfft_batch_schedule(lfft_batch_t plan, int i, int* passes, int64_t* pencil, 
 /* Autotuner: time every candidate configuration (tile_lg in {11, 12, 13},
  * order in {0, 1, 2, 3}) with the persistent launch on the caller's buffers
  * (reps timed runs each, minimum kept), keep the fastest, and remember it
- * for this process keyed by the list of matrices: a later call with the
- * same matrices applies the remembered choice without timing
- * (*best_ms = -1).  Overwrites out and the workspace.  Synchronises. */
+ * for this process keyed by the device architecture, the plan flags and
+ * the list of matrices: a later call with the same key applies the
+ * remembered choice without timing (*best_ms = -1).  Overwrites out and the
+ * workspace.  Synchronises. */
 int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspace, int reps,
                     float* best_ms, hipStream_t stream);
+
+/* The tuner's choices on disk, so that they survive the process.  Every
+ * choice is remembered under the device architecture it was timed on (e.g.
+ * "gfx950", without feature suffixes), the plan flags and the exact list of
+ * matrices.  lfft_batch_tune_save writes every choice this process holds
+ * (tuned or loaded) to `path` as JSON:
+ *   {"format": "lfft-batch-tune", "version": 1, "entries": [
+ *     {"arch": "gfx950", "d": 2, "flags": 0, "matrices": [row-major, every
+ *      lattice's d x d matrix concatenated], "tile_lg": 13, "order": 3,
+ *      "ms": 0.455}, ...]}
+ * (ms: the tuned time, -1 if unknown).  Errors: ARG (null or empty path),
+ * IO (cannot write). */
+int lfft_batch_tune_save(const char* path);
+
+/* Merge the entries of a file written by lfft_batch_tune_save whose arch
+ * equals `arch` (NULL: the current device's architecture) into this
+ * process's choices, replacing choices with the same key; lfft_batch_tune on
+ * those matrices and flags then applies them without timing.  The whole file
+ * is validated first: a malformed file changes nothing.  *loaded (may be
+ * NULL) receives the number of entries taken.  Errors: ARG (null or empty
+ * path), IO (cannot read, or not such a file), HIP (arch NULL and no
+ * device). */
+int lfft_batch_tune_load(const char* path, const char* arch, int* loaded);
+
+/* Forget every remembered choice of this process; *count (may be NULL)
+ * receives how many there were. */
+int lfft_batch_tune_clear(int* count);
 
 /* out = F(M_i) in (inverse != 0: F(M_i)^{-1}) for every lattice, in device
  * complex64 [sum m_i], out of place, on `stream`.  mode: LFFT_BATCH_*.

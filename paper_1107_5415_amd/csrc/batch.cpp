@@ -8,6 +8,7 @@
 
 #include "kernels.hpp"
 #include "ktrace.hpp"
+#include "tune_cache.hpp"
 
 namespace lfft {
 
@@ -201,14 +202,6 @@ void enqueue_persistent(BatchPlan* b, bool inverse, const void* in, void* out, v
   }
 }
 
-struct TuneKey {
-  int d;
-  std::vector<i64> Ms;
-  bool operator<(const TuneKey& o) const { return std::tie(d, Ms) < std::tie(o.d, o.Ms); }
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;
-
 }  // namespace
 
 BatchPlan* build_batch_plan(int count, int d, const i64* Ms, uint32_t flags) {
@@ -368,16 +361,17 @@ void exec_batch(BatchPlan* b, bool inverse, int mode, const void* in, void* out,
 void tune_batch(BatchPlan* b, const void* in, void* out, void* ws, int reps, hipStream_t s,
                 float* best_ms) {
   if (!b->dheads || reps < 1) throw StatusError{E_ARG};
-  TuneKey key{b->d, b->Ms};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      if (it->second != std::make_pair(b->tile_lg, b->order) || !b->configured)
-        configure_batch(b, it->second.first, it->second.second);
-      if (best_ms) *best_ms = -1.0f;
-      return;
-    }
+  TuneKey key;
+  key.arch = device_arch();
+  key.d = b->d;
+  key.flags = b->flags;
+  key.Ms = b->Ms;
+  TuneVal known;
+  if (tune_cache_find(key, &known)) {
+    if (known.tile_lg != b->tile_lg || known.order != b->order || !b->configured)
+      configure_batch(b, known.tile_lg, known.order);
+    if (best_ms) *best_ms = -1.0f;
+    return;
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -413,10 +407,7 @@ void tune_batch(BatchPlan* b, const void* in, void* out, void* ws, int reps, hip
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   configure_batch(b, arg.first, arg.second);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = arg;
-  }
+  tune_cache_put(key, TuneVal{arg.first, arg.second, best});
   if (best_ms) *best_ms = best;
 }
 

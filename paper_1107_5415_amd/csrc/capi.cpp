@@ -7,6 +7,7 @@
 
 #include "batch.hpp"
 #include "handles.hpp"
+#include "tune_cache.hpp"
 #include "plan.hpp"
 #include "wave.hpp"
 
@@ -409,6 +410,26 @@ int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspac
   return guarded([&] { lfft::tune_batch(plan->b, in, out, workspace, reps, stream, best_ms); });
 }
 
+int lfft_batch_tune_save(const char* path) {
+  if (!path || !*path) return LFFT_E_ARG;
+  return guarded([&] { lfft::tune_cache_save(path); });
+}
+
+int lfft_batch_tune_load(const char* path, const char* arch, int* loaded) {
+  if (!path || !*path) return LFFT_E_ARG;
+  return guarded([&] {
+    const std::string a = arch ? std::string(arch) : lfft::device_arch();
+    const int n = lfft::tune_cache_load(path, a);
+    if (loaded) *loaded = n;
+  });
+}
+
+int lfft_batch_tune_clear(int* count) {
+  if (count) *count = lfft::tune_cache_size();
+  lfft::tune_cache_clear();
+  return LFFT_OK;
+}
+
 int lfft_batch_execute(lfft_batch_t plan, int inverse, int mode, const void* in, void* out,
                        void* workspace, hipStream_t stream) {
   if (!plan || !in || !out || in == out || !workspace) return LFFT_E_ARG;
@@ -428,6 +449,7 @@ const char* lfft_strerror(int status) {
     case LFFT_E_HIP: return "HIP runtime error";
     case LFFT_E_NOMEM: return "device allocation failed";
     case LFFT_E_STATE: return "invalid plan state";
+    case LFFT_E_IO: return "file not readable or writable, or not a tuning cache";
     default: return "unknown status";
   }
 }

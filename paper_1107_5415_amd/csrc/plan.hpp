@@ -21,6 +21,7 @@ enum Status : int {
   E_HIP = -6,
   E_NOMEM = -7,
   E_STATE = -8,
+  E_IO = -9,
 };
 
 // plan flags (mirrors include/lfft.h)

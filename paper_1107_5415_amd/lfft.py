@@ -44,7 +44,7 @@ EXPORTS = [
     "lfft_batch_offsets", "lfft_batch_workspace_size", "lfft_batch_configure", "lfft_batch_config",
     "lfft_batch_schedule", "lfft_batch_tune", "lfft_batch_execute", "lfft_points",
     "lwt_fiber_map", "lwt_coeff_layout", "lfft_forward_noalloc", "lfft_basis_workspace_size",
-    "lfft_basis_change",
+    "lfft_basis_change", "lfft_batch_tune_save", "lfft_batch_tune_load", "lfft_batch_tune_clear",
 ]
 
 LFFT_BATCH_LOOP = 0
@@ -119,6 +119,9 @@ def lib():
             "lwt_fiber_map": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                              ctypes.c_int64, _I64P, _I64P]),
             "lwt_coeff_layout": (ctypes.c_int, [_P, _I32P, _I32P, _I64P, _I64P, _I32P, _I32P]),
+            "lfft_batch_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+            "lfft_batch_tune_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_char_p, _I32P]),
+            "lfft_batch_tune_clear": (ctypes.c_int, [_I32P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -580,6 +583,27 @@ class BatchPlan:
         _check(lib().lfft_batch_tune(self._h, _dptr(x), _dptr(out), _dptr(ws), int(reps),
                                      ctypes.byref(best), _stream_handle(x.device)), "lfft_batch_tune")
         return best.value
+
+
+def tune_save(path):
+    """Write every remembered autotuner choice to `path` (lfft_batch_tune_save)."""
+    _check(lib().lfft_batch_tune_save(os.fsencode(path)), "lfft_batch_tune_save")
+
+
+def tune_load(path, arch=None):
+    """Merge the choices for `arch` (None: the current device's) from a file
+    written by tune_save; returns how many were taken (lfft_batch_tune_load)."""
+    n = ctypes.c_int()
+    _check(lib().lfft_batch_tune_load(os.fsencode(path), None if arch is None else arch.encode(),
+                                      ctypes.byref(n)), "lfft_batch_tune_load")
+    return n.value
+
+
+def tune_clear():
+    """Forget every remembered autotuner choice; returns how many there were."""
+    n = ctypes.c_int()
+    _check(lib().lfft_batch_tune_clear(ctypes.byref(n)), "lfft_batch_tune_clear")
+    return n.value
 
 
 def trace_begin(capacity=100000):

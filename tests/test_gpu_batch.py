@@ -98,7 +98,7 @@ def test_batch_graph_replays():
         torch.cuda.synchronize()
 
 
-def test_batch_workload_tuned():
+def test_batch_workload_tuned(tmp_path):
     """The batched workload (512 lattices [[2^a, c], [0, 2^b]], a + b in
     10..18): autotuned, graph mode, every lattice against the oracle, and
     the per-lattice launches agree."""
@@ -122,3 +122,11 @@ def test_batch_workload_tuned():
     plan2 = lfft.BatchPlan(Ms)
     assert plan2.tune(x, reps=1) == -1.0
     assert plan2.config() == cfg
+    # and survives the process through the cache file
+    path = str(tmp_path / "tune.json")
+    lfft.tune_save(path)
+    assert lfft.tune_clear() >= 1
+    assert lfft.tune_load(path) >= 1
+    plan3 = lfft.BatchPlan(Ms)
+    assert plan3.tune(x, reps=1) == -1.0
+    assert plan3.config() == cfg

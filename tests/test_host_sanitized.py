@@ -4,7 +4,8 @@ Builds a second copy of the library whose host sources (the exact integer
 planner, the pyramid driver, the batch scheduler, the C ABI) are compiled
 with g++ -fsanitize=address,undefined and linked with the unmodified gfx950
 objects of the regular build, then runs the CPU ctypes tests of
-test_host_planner.py against it in a child process (the library is selected
+test_host_planner.py and test_host_tune_cache.py (the tuning cache's JSON
+reader on good and malformed files) against it in a child process (the library is selected
 with LFFT_LIBRARY).  Any sanitizer report aborts the child and fails the test.
 No GPU is used: every plan in those tests is host-only.
 """
@@ -19,7 +20,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1107_5415_amd", "csrc")
 OBJ = os.path.join(ROOT, "_build")
 OUT = os.path.join(ROOT, "_build", "sanitized")
-HOST_SOURCES = ["intmat.cpp", "plan.cpp", "capi.cpp", "batch.cpp", "ktrace.cpp", "wave.cpp"]
+HOST_SOURCES = ["intmat.cpp", "plan.cpp", "capi.cpp", "batch.cpp", "ktrace.cpp", "wave.cpp",
+                "tune_cache.cpp"]
 FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "-fsanitize=address,undefined",
          "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", "-D__HIP_PLATFORM_AMD__",
          "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
@@ -73,7 +75,8 @@ def test_host_planner_sanitized():
                ASAN_OPTIONS="detect_leaks=0:protect_shadow_gap=0:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_host_planner.py")],
+                        os.path.join(ROOT, "tests", "test_host_planner.py"),
+                        os.path.join(ROOT, "tests", "test_host_tune_cache.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     tail = (r.stdout + r.stderr)[-4000:]
     assert r.returncode == 0, tail
