@@ -311,6 +311,89 @@ def variant_q4(torch, lfft, reps):
             **res}
 
 
+# Section 6.1, Table 1: seconds of the lattice FFT of 2^22 random values on
+# M = [[2048, i], [0, 2048]], serial and on four cores of the paper's 2 GHz
+# quad-core CPU (context for the rows below, not a target)
+PAPER_TABLE1_S = {1: (0.266664, 0.270647), 2: (0.471722, 0.343969), 4: (0.468220, 0.299426),
+                  8: (0.457126, 0.282309), 16: (0.457321, 0.286432), 32: (0.469080, 0.299551),
+                  64: (0.466902, 0.315000), 128: (0.572192, 0.412570), 256: (0.920226, 0.741036),
+                  512: (1.144126, 0.530716), 1024: (0.949403, 0.424802), 0: (0.907286, 0.411705)}
+
+
+def variant_table1(torch, lfft, reps, check):
+    """The paper's timing table (Section 6.1): forward lattice FFT of m = 2^22
+    complex64 values, natural orders, on M = [[2048, i], [0, 2048]] for every
+    row i, beside the paper's serial and four-core seconds."""
+    import numpy as np
+    import workloads
+    cfg = workloads.CONFIGS["table1"]
+    m = 1 << 22
+    xh = workloads.complex_normal(cfg["seed"], m)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+    rows = []
+    worst = None
+    for i in cfg["i"]:
+        M = workloads.table1_matrix(i)
+        plan = lfft.LatticePlan(M)
+        t = _time_ms(lambda: plan.forward(x, out=y), reps, torch)
+        serial, par = PAPER_TABLE1_S[i]
+        row = {"i": i, "eps": [int(e) for e in plan.query()["eps"] if e > 1],
+               "passes": int(plan.query()["passes"]), "ms": round(t, 4),
+               "gflops": round(fft_flops(m) / (t / 1e3) / 1e9, 1),
+               "alg_hbm_frac": round(16.0 * m / (t / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+               "paper_serial_s": serial, "paper_4core_s": par}
+        if check:
+            from oracle import dft
+            plan.forward(x, out=y)
+            e = errors(y.cpu().numpy(), dft.lattice_dft_hnf(M, xh.astype(np.complex128),
+                                                          workers=host_cores()))
+            row["error_vs_oracle"] = e
+            worst = e["rel_l2"] if worst is None else max(worst, e["rel_l2"])
+        rows.append(row)
+        del plan
+    out = {"workload": "M=[[2048,i],[0,2048]] for the 12 rows of the paper's timing table, m=2^22 "
+                       "complex64 N(0,1) seed %d, forward FFT natural order" % cfg["seed"],
+           "rows": rows}
+    if worst is not None:
+        out["worst_rel_l2_vs_oracle"] = worst
+    return out
+
+
+def variant_dirichlet_1level(torch, lfft, reps, check):
+    """The wavelet experiment of Section 6.2 without its box splines: point
+    values on M = diag(512, 512) (random stand-ins for the sampled box
+    splines), changed into orthonormal-translate coefficients and split once
+    with each dilation J_x, J_y, J_d; decomposition and reconstruction."""
+    import numpy as np
+    import workloads
+    cfg = workloads.CONFIGS["dirichlet_1level"]
+    M = cfg["M"]
+    m = 512 * 512
+    sh = workloads.complex_normal(cfg["seed"], m)
+    s = torch.from_numpy(sh).cuda()
+    res = {}
+    for name, J in zip(("J_x", "J_y", "J_d"), cfg["J"]):
+        plan = lfft.WaveletPlan(M, J, 1, samples=True)
+        masks = plan.dirichlet_masks(torch.device("cuda:0"))
+        c = torch.empty_like(s)
+        r = torch.empty_like(s)
+        td = _time_ms(lambda: plan.decompose(s, masks, out=c), reps, torch)
+        tr = _time_ms(lambda: plan.reconstruct(c, masks, out=r), reps, torch)
+        row = {"decompose_ms": round(td, 4), "reconstruct_ms": round(tr, 4),
+               "rel_l2_roundtrip": float(torch.linalg.norm(r - s) / torch.linalg.norm(s))}
+        if check:
+            from oracle import interp, wavelet
+            plan.decompose(s, masks, out=c)
+            a = interp.samples_to_coeffs(M, sh.astype(np.complex128))
+            row["error_vs_oracle"] = errors(c.cpu().numpy(), wavelet.decompose(a, M, J, 1))
+        res[name] = row
+        del plan
+    return {"workload": "M=diag(512,512) point values complex64 N(0,1) seed %d, basis change to "
+                        "orthonormal translates + one Dirichlet level per dilation" % cfg["seed"],
+            **res}
+
+
 def aggregate(trace, steps):
     """Per kernel: launches per step, ms per step, method and pass bytes."""
     agg = {}
@@ -544,12 +627,17 @@ def main():
                                      wavelet.reconstruct(Ch.astype(np.complex128), M, J, levels))}
         out["error_vs_oracle"] = acc
     if not args.no_variants:
-        log("bench: variants (split-BF16, batched, differentiation)")
+        log("bench: variants (split-BF16, batched, differentiation, four channels, timing table, "
+            "one Dirichlet level)")
         check = not args.no_check
         out["variants"] = {"split_bf16": variant_split_bf16(torch, lfft, max(5, args.steps // 2), check),
                            "batched": variant_batched(torch, lfft, max(5, args.steps // 2), check),
                            "grad": variant_grad(torch, lfft, max(3, args.steps // 4), check),
-                           "q4": variant_q4(torch, lfft, max(5, args.steps // 2))}
+                           "q4": variant_q4(torch, lfft, max(5, args.steps // 2)),
+                           "table1": variant_table1(torch, lfft, max(5, args.steps // 2), check),
+                           "dirichlet_1level": variant_dirichlet_1level(torch, lfft,
+                                                                        max(5, args.steps // 2),
+                                                                        check)}
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, m)

@@ -38,6 +38,14 @@ CONFIGS = {
     # four channels per level: the large M with J = 2 I, 4 levels (the same
     # final resolution m_L = 2^16 as 8 quincunx levels)
     "q4": dict(M=((4096, 2048), (0, 4096)), J=J_2I, levels=4, batch=1, seed=7),
+    # the timing table of Section 6.1: M = [[2048, i], [0, 2048]], m = 2^22,
+    # for every divisor i of 2048 and i = 0 (see table1_matrix)
+    "table1": dict(M=None, J=None, levels=0, batch=1, seed=8,
+                   i=(1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 0)),
+    # the wavelet experiment of Section 6.2 without its box splines: point
+    # values on M = diag(512, 512), one level for each dilation of J_x, J_y, J_d
+    "dirichlet_1level": dict(M=((512, 0), (0, 512)), J=(J_X, J_Y, J_D), levels=1, batch=1,
+                             seed=9),
 }
 
 
