@@ -66,6 +66,14 @@ extern "C" {
 #define LFFT_E_IO (-9)           /* a file could not be read or written, or is
                                     not a tuning cache                        */
 
+/* ---- plan log -------------------------------------------------------------
+ * With the environment variable LFFT_LOG set to anything but "0" (read once,
+ * at the first plan), lfft_plan_create, lwt_plan_create and the lfft_batch_*
+ * create/configure/tune calls print the schedule of the plan to stderr: the
+ * elementary divisors, the pass count and, per pass of the natural-order
+ * forward and inverse transforms, the kernel and its pencil shape; for a
+ * pyramid every level's channel grid and which levels are batched. */
+
 /* ---- plan flags --------------------------------------------------------- */
 #define LFFT_HOST_ONLY 0x1u      /* integer planning only: no device tables,
                                     execute calls return LFFT_E_STATE         */

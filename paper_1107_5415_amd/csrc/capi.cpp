@@ -7,6 +7,7 @@
 
 #include "batch.hpp"
 #include "handles.hpp"
+#include "planlog.hpp"
 #include "tune_cache.hpp"
 #include "plan.hpp"
 #include "wave.hpp"
@@ -78,6 +79,7 @@ int lfft_plan_create(lfft_plan_t* plan, int d, const int64_t* M, int64_t batch, 
     lfft::free_plan(p);
     return LFFT_E_NOMEM;
   }
+  lfft::log_lattice_plan(p, "plan");
   return LFFT_OK;
 }
 
@@ -202,6 +204,7 @@ int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J,
     lfft::free_wave_plan(w);
     return LFFT_E_NOMEM;
   }
+  lfft::log_wave_plan(w);
   return LFFT_OK;
 }
 
@@ -354,6 +357,7 @@ int lfft_batch_create(lfft_batch_t* plan, int count, int d, const int64_t* Ms, u
     lfft::free_batch_plan(b);
     return LFFT_E_NOMEM;
   }
+  lfft::log_batch_plan(b, "batch");
   return LFFT_OK;
 }
 
@@ -377,7 +381,10 @@ size_t lfft_batch_workspace_size(lfft_batch_t plan) {
 
 int lfft_batch_configure(lfft_batch_t plan, int tile_lg, int order) {
   if (!plan) return LFFT_E_ARG;
-  return guarded([&] { lfft::configure_batch(plan->b, tile_lg, order); });
+  return guarded([&] {
+    lfft::configure_batch(plan->b, tile_lg, order);
+    lfft::log_batch_plan(plan->b, "batch configured:");
+  });
 }
 
 int lfft_batch_config(lfft_batch_t plan, int* tile_lg, int* order, int* eligible) {
@@ -407,7 +414,10 @@ int lfft_batch_tune(lfft_batch_t plan, const void* in, void* out, void* workspac
                     float* best_ms, hipStream_t stream) {
   if (!plan || !in || !out || in == out || !workspace || reps < 1) return LFFT_E_ARG;
   if (!plan->b->dheads) return LFFT_E_STATE;
-  return guarded([&] { lfft::tune_batch(plan->b, in, out, workspace, reps, stream, best_ms); });
+  return guarded([&] {
+    lfft::tune_batch(plan->b, in, out, workspace, reps, stream, best_ms);
+    lfft::log_batch_plan(plan->b, "batch tuned:");
+  });
 }
 
 int lfft_batch_tune_save(const char* path) {

@@ -1,0 +1,52 @@
+"""The plan log (LFFT_LOG): host-only plans print their schedule to stderr
+when the variable is set, and nothing otherwise.  Runs in child processes,
+since the library reads the variable once."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CHILD = r"""
+import sys
+sys.path.insert(0, %r)
+from paper_1107_5415_amd import lfft
+import workloads
+cfg = workloads.CONFIGS["large"]
+lfft.LatticePlan(cfg["M"], host_only=True)
+lfft.WaveletPlan(cfg["M"], cfg["J"], 3, host_only=True)
+lfft.BatchPlan(workloads.batched_matrices(count=8), host_only=True)
+""" % ROOT
+
+
+def run(env_value):
+    env = dict(os.environ)
+    env.pop("LFFT_LOG", None)
+    if env_value is not None:
+        env["LFFT_LOG"] = env_value
+    r = subprocess.run([sys.executable, "-c", CHILD], env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    return r.stderr
+
+
+def test_log_prints_the_schedule():
+    err = run("1")
+    lines = [l for l in err.splitlines() if l.startswith("lfft:")]
+    assert any("plan d=2 m=16777216" in l and "eps=2048x8192 passes=2" in l for l in lines), err
+    # the two forward passes of the large workload: rows over the 8192-cycle
+    # from the natural samples, then 8-column tiles onto natural frequencies
+    assert any("forward  pass 1/2 fft_stream_kernel<8192, 1, false, false, 2, 0>" in l
+               for l in lines), err
+    assert any("forward  pass 2/2 fft_stream_kernel<2048, 8, true, false, 0, 2>" in l
+               for l in lines), err
+    assert any("inverse  pass 2/2" in l and "natural out" in l for l in lines), err
+    assert any(l.startswith("lfft: pyramid d=2 m=16777216") and "q=2 levels=3" in l
+               for l in lines), err
+    assert sum("  level " in l for l in lines) == 3
+    assert any(l.startswith("lfft: batch lattices=8") for l in lines), err
+
+
+def test_log_is_silent_by_default():
+    assert "lfft:" not in run(None)
+    assert "lfft:" not in run("0")

@@ -21,7 +21,7 @@ CSRC = os.path.join(ROOT, "paper_1107_5415_amd", "csrc")
 OBJ = os.path.join(ROOT, "_build")
 OUT = os.path.join(ROOT, "_build", "sanitized")
 HOST_SOURCES = ["intmat.cpp", "plan.cpp", "capi.cpp", "batch.cpp", "ktrace.cpp", "wave.cpp",
-                "tune_cache.cpp"]
+                "tune_cache.cpp", "planlog.cpp"]
 FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "-fsanitize=address,undefined",
          "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", "-D__HIP_PLATFORM_AMD__",
          "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
