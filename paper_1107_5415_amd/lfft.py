@@ -315,6 +315,52 @@ def inverse(x, M):
     return get_plan(M, b).inverse(x).reshape(x.shape)
 
 
+_wave_cache = {}
+_mask_cache = {}
+
+
+def _wave_key(M, J, levels, batch):
+    return (tuple(map(tuple, _mat(M).tolist())), tuple(map(tuple, _mat(J).tolist())), int(levels),
+            int(batch))
+
+
+def get_wavelet_plan(M, J, levels, batch=1):
+    key = _wave_key(M, J, levels, batch)
+    p = _wave_cache.get(key)
+    if p is None:
+        p = WaveletPlan(M, J, levels, batch)
+        _wave_cache[key] = p
+    return p
+
+
+def _pyramid(x, M, J, levels, masks):
+    m = x.shape[-1]
+    b = x.numel() // m
+    key = _wave_key(M, J, levels, b)
+    plan = get_wavelet_plan(M, J, levels, b)
+    if masks is None:
+        mk = (key, str(x.device))
+        if mk not in _mask_cache:
+            _mask_cache[mk] = plan.dirichlet_masks(x.device)
+        masks = _mask_cache[mk]
+    return plan, masks
+
+
+def decompose(x, M, J, levels, masks=None):
+    """Wavelet pyramid coefficients of x (complex64 [..., m], natural sample
+    order of M) for `levels` splits M_l = J M_{l+1}; masks: one float32
+    device tensor per level in natural G(M_l^T) order (None: the Dirichlet
+    masks).  The coefficient layout is WaveletPlan.coeff_blocks()."""
+    plan, masks = _pyramid(x, M, J, levels, masks)
+    return plan.decompose(x.reshape(-1), masks).reshape(x.shape)
+
+
+def reconstruct(c, M, J, levels, masks=None):
+    """Inverse of decompose (same arguments)."""
+    plan, masks = _pyramid(c, M, J, levels, masks)
+    return plan.reconstruct(c.reshape(-1), masks).reshape(c.shape)
+
+
 class WaveletPlan:
     """Plan of the multi-level lattice wavelet pyramid (lwt_plan_*)."""
 
