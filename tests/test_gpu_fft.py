@@ -43,6 +43,9 @@ CASES = [
     ("d3_small", ((3, 1, 0), (0, 3, 1), (1, 0, 3)), 2),
     ("d3_mixed", ((6, 0, 0), (0, 10, 0), (0, 0, 15)), 1),
     ("d4_small", ((2, 1, 0, 0), (0, 3, 1, 0), (1, 0, 4, 1), (0, 1, 0, 5)), 1),
+    # four dimensions beyond one tile: several passes with 4-D natural maps
+    ("d4_sheared_multi_pass", ((16, 4, 0, 0), (0, 16, 4, 0), (0, 0, 16, 4), (0, 0, 0, 32)), 1),
+    ("d4_lower_mixed", ((12, 0, 0, 0), (3, 10, 0, 0), (0, 5, 14, 0), (1, 0, 7, 18)), 2),
     ("two_pass_2^14", ((128, 32), (0, 128)), 2),
     ("two_pass_odd", ((105, 0), (0, 1287)), 1),
     ("split_then_axis_d3", ((16, 0, 0), (0, 1024, 3), (0, 0, 1024)), 1),

@@ -28,6 +28,9 @@ CASES = [
     ("example1", ((4, -3), (4, 5)), workloads.J_D, 1, 2),
     ("d3", ((6, 2, 0), (0, 4, 2), (0, 0, 6)), ((2, 0, 0), (0, 1, 0), (0, 0, 1)), 1, 1),
     ("two_pass_levels", ((256, 64), (0, 256)), workloads.J_QUINCUNX, 4, 1),
+    # four dimensions: two levels of J = diag(2, 1, 1, 1) on a sheared M
+    ("d4_levels", ((8, 4, 0, 0), (0, 8, 2, 0), (0, 0, 8, 2), (0, 0, 0, 8)),
+     ((2, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)), 2, 2),
 ]
 
 
