@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import dft, grad as G, lattice as L, wavelet as W
+from oracle import dft, grad as G, lattice as L, wavelet as W, wavelet_q as WQ
 import workloads
 
 
@@ -45,7 +45,41 @@ def test_pyramid_forward_matches_oracle(M, J, levels):
                                W.reconstruct(c, M, J, levels), atol=1e-12)
 
 
-@pytest.mark.parametrize("M,J,levels", CASES)
+# q = |det J| > 2: four channels (J = 2I), three (J = diag(3, 1)), eight in 3-D
+QCASES = [(((16, 8), (0, 16)), workloads.J_2I, 2), (((27, 9), (0, 9)), ((3, 0), (0, 1)), 2),
+          (((8, 4, 0), (0, 8, 4), (0, 0, 8)), ((2, 0, 0), (0, 2, 0), (0, 0, 2)), 1)]
+
+
+@pytest.mark.parametrize("M,J,levels", QCASES)
+def test_pyramid_q_forward_matches_oracle(M, J, levels):
+    """The torch q-channel pyramid equals oracle.wavelet_q, with the Dirichlet
+    masks and with perturbed (non-QMF) masks."""
+    m = abs(L.det(M))
+    rng = np.random.default_rng(11)
+    x = workloads.complex_normal(12, (2, m), np.complex128)
+    pyr = G.TorchPyramidQ(M, J, levels)
+    for masks in (WQ.default_masks(M, J, levels),
+                  [mk + 0.2 * rng.standard_normal(mk.shape) for mk in WQ.default_masks(M, J, levels)]):
+        mt = [torch.from_numpy(mk) for mk in masks]
+        c = pyr.decompose(torch.from_numpy(x), mt).numpy()
+        np.testing.assert_allclose(c, WQ.decompose(x, M, J, levels, masks=masks), atol=1e-12)
+        np.testing.assert_allclose(pyr.reconstruct(torch.from_numpy(c), mt).numpy(),
+                                   WQ.reconstruct(c, M, J, levels, masks=masks), atol=1e-12)
+
+
+@pytest.mark.parametrize("M,J,levels", QCASES)
+def test_pyramid_q_parseval_gradient(M, J, levels):
+    """With the Dirichlet masks the q-channel pyramid is unitary, so
+    grad_x ||D x||^2 = 2 x."""
+    m = abs(L.det(M))
+    x = torch.from_numpy(workloads.complex_normal(13, (1, m), np.complex128)).requires_grad_(True)
+    pyr = G.TorchPyramidQ(M, J, levels)
+    c = pyr.decompose(x, [torch.from_numpy(mk) for mk in WQ.default_masks(M, J, levels)])
+    torch.sum(c.real ** 2 + c.imag ** 2).backward()
+    np.testing.assert_allclose(x.grad.numpy(), 2 * x.detach().numpy(), atol=1e-11)
+
+
+@pytest.mark.parametrize("M,J,levels", CASES + QCASES)
 def test_gradients_finite_differences(M, J, levels):
     """Central differences in FP64 along random directions of the samples and
     of the (non-QMF, perturbed) masks."""
@@ -53,10 +87,12 @@ def test_gradients_finite_differences(M, J, levels):
     rng = np.random.default_rng(4)
     x = workloads.complex_normal(5, (2, m), np.complex128)
     target = workloads.complex_normal(6, (2, m), np.complex128)
-    masks = [mk + 0.1 * rng.standard_normal(mk.shape) for mk in W.default_masks(M, J, levels)]
+    q = abs(L.det(L.as_matrix(J)))
+    base = W.default_masks(M, J, levels) if q == 2 else WQ.default_masks(M, J, levels)
+    masks = [mk + 0.1 * rng.standard_normal(mk.shape) for mk in base]
     weights = [1.0 + 0.5 * l for l in range(levels)]
     loss, gx, gm = G.loss_and_grads(M, J, levels, x, masks, target, weights)
-    pyr = G.TorchPyramid(M, J, levels)
+    pyr = G.make_pyramid(M, J, levels)
 
     def Lf(xx, mm):
         with torch.no_grad():
@@ -68,6 +104,9 @@ def test_gradients_finite_differences(M, J, levels):
     an = float(np.sum((np.conj(gx) * v).real))
     assert abs(fd - an) <= 1e-9 * max(1.0, abs(an))
     u = [rng.standard_normal(mk.shape) for mk in masks]
+    # quadratic in each mask for q = 2; through the reflection for q > 2 the
+    # loss is smooth but not quadratic, and the O(h^2) term stays far below
+    # the tolerance at this step
     h = 1e-5
     fd = (Lf(x, [a + h * b for a, b in zip(masks, u)]) - Lf(x, [a - h * b for a, b in zip(masks, u)])) / (2 * h)
     an = float(sum(np.sum(g * b) for g, b in zip(gm, u)))
