@@ -54,8 +54,7 @@ extern "C" {
 #define LFFT_E_SINGULAR (-2)     /* det M = 0                                 */
 #define LFFT_E_NOT_INTEGRAL (-3) /* J^{-1} M not integral at some level       */
 #define LFFT_E_OVERFLOW (-4)     /* exact integer work would exceed int64     */
-#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, mask
-                                    gradients with |det J| > 2, or an
+#define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, or an
                                     elementary divisor above 2^23 that cannot
                                     be split into two factors of at most 8192
                                     (shorter ones run as a chirp-z pass)     */
@@ -228,9 +227,9 @@ int lfft_basis_change(lfft_plan_t plan, int direction, int fourier, const void* 
  * classes in the natural order of the Hermite box of J^T) has first row
  * u = (a(h_l) / sqrt q)_l and the other rows from the reflection
  * I - 2 v v^T / (v^T v), v = u + sign(u_0) e_0 (sign(0) = +1); it is
- * orthogonal when the mask satisfies sum_l a(h_l)^2 = q.  q > 2 supports
- * lwt_decompose / lwt_reconstruct with saved = NULL, and the two adjoints
- * without mask gradients (grad_masks = NULL).  Errors: ARG,
+ * orthogonal when the mask satisfies sum_l a(h_l)^2 = q.  The mask
+ * gradients of q > 2 differentiate through the reflection (sign(u_0) held
+ * constant on each fiber).  Errors: ARG,
  * SINGULAR, NOT_INTEGRAL, OVERFLOW, UNSUPPORTED (q > 16, d > 4), NOMEM,
  * HIP.  flags: 0, LFFT_HOST_ONLY, LWT_SINGLE_STREAM. */
 int lwt_plan_create(lwt_plan_t* plan, int d, const int64_t* M, const int64_t* J, int levels,
@@ -290,7 +289,7 @@ int lwt_coeff_layout(lwt_plan_t plan, int* q, int* nblocks, int64_t* offset, int
 int lwt_dirichlet_mask(lwt_plan_t plan, int level, float* mask);
 
 /* Workspace bytes of every lwt_* execute call, and complex64 elements of
- * the `saved` buffer used for differentiation (0 for q > 2). */
+ * the `saved` buffer used for differentiation (batch * sum_l m_l). */
 size_t lwt_workspace_size(lwt_plan_t plan);
 size_t lwt_saved_elems(lwt_plan_t plan);
 
@@ -304,22 +303,23 @@ size_t lwt_saved_elems(lwt_plan_t plan);
  * float[m_l] in NATURAL order of G(M_l^T) (real scaling symbol; the wavelet
  * symbol is derived from it).  saved: NULL or device complex64 buffer of
  * lwt_saved_elems() receiving the per-level Fourier inputs (needed by
- * lwt_decompose_backward for mask gradients). */
+ * lwt_decompose_backward for mask gradients; for q > 2 the decomposition
+ * then also runs every level's channels one level at a time). */
 int lwt_decompose(lwt_plan_t plan, const void* samples, const float* const* masks, void* coeffs,
                   void* saved, void* workspace, hipStream_t stream);
 
 /* Reconstruction (inverse of lwt_decompose; synthesis gamma = sum_j sum_y
  * d_{j,y} T(y) g_j of Section 5.3).  saved: NULL or buffer of
- * lwt_saved_elems() receiving the per-level (d1hat, d2hat) for
+ * lwt_saved_elems() receiving the per-level synthesis inputs (q = 2:
+ * d1hat, d2hat; q > 2: channel 0, then channels 1 .. q-1) for
  * lwt_reconstruct_backward. */
 int lwt_reconstruct(lwt_plan_t plan, const void* coeffs, const float* const* masks, void* samples,
                     void* saved, void* workspace, hipStream_t stream);
 
 /* Adjoint of lwt_decompose: grad_samples = D^H grad_coeffs, and, if
  * grad_masks (host array of device pointers) is non-NULL, d loss / d mask_l
- * summed over the batch, using `saved` from lwt_decompose.  For q > 2 only
- * the sample gradient (grad_masks = NULL, saved ignored; UNSUPPORTED
- * otherwise), as in lwt_reconstruct_backward. */
+ * summed over the batch, using `saved` from lwt_decompose (ARG if NULL).
+ * Gradients follow the convention G = dL/dRe + i dL/dIm. */
 int lwt_decompose_backward(lwt_plan_t plan, const void* grad_coeffs, const void* saved,
                            const float* const* masks, void* grad_samples, float* const* grad_masks,
                            void* workspace, hipStream_t stream);

@@ -60,7 +60,10 @@ class WaveletDecompose(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, plan, *masks):
-        saved = plan.new_saved(x.device) if plan.q == 2 else None
+        # the saved Fourier inputs are needed for mask gradients (and, for
+        # q = 2, the saved path is the one-launch-per-level schedule)
+        keep = plan.q == 2 or any(ctx.needs_input_grad[2:])
+        saved = plan.new_saved(x.device) if keep else None
         c = plan.decompose(x.contiguous(), list(masks), saved=saved)
         ctx.plan = plan
         ctx.save_for_backward(saved, *masks)
@@ -81,7 +84,8 @@ class WaveletReconstruct(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, c, plan, *masks):
-        saved = plan.new_saved(c.device) if plan.q == 2 else None
+        keep = plan.q == 2 or any(ctx.needs_input_grad[2:])
+        saved = plan.new_saved(c.device) if keep else None
         x = plan.reconstruct(c.contiguous(), list(masks), saved=saved)
         ctx.plan = plan
         ctx.save_for_backward(saved, *masks)

@@ -320,7 +320,6 @@ int lwt_decompose_backward(lwt_plan_t plan, const void* grad_coeffs, const void*
                            void* workspace, hipStream_t stream) {
   LWT_CHECK(plan, workspace);
   if (!grad_coeffs || !grad_samples || !masks || grad_coeffs == grad_samples) return LFFT_E_ARG;
-  if (grad_masks && plan->w->q != 2) return LFFT_E_UNSUPPORTED;
   if (grad_masks && !saved) return LFFT_E_ARG;
   return guarded([&] {
     lfft::wave_decompose_backward(plan->w, static_cast<const float2*>(grad_coeffs),
@@ -334,7 +333,6 @@ int lwt_reconstruct_backward(lwt_plan_t plan, const void* grad_samples, const vo
                              float* const* grad_masks, void* workspace, hipStream_t stream) {
   LWT_CHECK(plan, workspace);
   if (!grad_coeffs || !grad_samples || !masks || grad_coeffs == grad_samples) return LFFT_E_ARG;
-  if (grad_masks && plan->w->q != 2) return LFFT_E_UNSUPPORTED;
   if (grad_masks && !saved) return LFFT_E_ARG;
   return guarded([&] {
     lfft::wave_reconstruct_backward(plan->w, static_cast<const float2*>(grad_samples),

@@ -73,6 +73,20 @@ hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2*
                             long long d0_bs, const float2* dw, long long dw_bs, const float* mask,
                             float2* ahat, long long ah_bs, hipStream_t s);
 
+// d loss / d mask of the q-channel split (x = ahat [B][m_l], incoming
+// gradients g0 of channel 0 [B][m_l/q] and gw of channels 1 .. q-1, layouts
+// as in launch_split_q) and of its synthesis (saved inputs d0, dw as in
+// launch_unsplit_q, incoming gradient g of ahat [B][m_l]); summed over the
+// batch, one writer per mask entry.
+hipError_t launch_split_q_mask_grad(const SplitQDesc& sd, long long batch, const float2* ahat,
+                                    long long ah_bs, const float* mask, const float2* g0,
+                                    long long g0_bs, const float2* gw, long long gw_bs,
+                                    float* gmask, hipStream_t s);
+hipError_t launch_unsplit_q_mask_grad(const SplitQDesc& sd, long long batch, const float2* d0,
+                                      long long d0_bs, const float2* dw, long long dw_bs,
+                                      const float* mask, const float2* g, long long g_bs,
+                                      float* gmask, hipStream_t s);
+
 // Chirp-z pass (kind 4), three steps around the inner FFTs of length p.bN:
 // A[pen][j] = x(pen, j) chirp[j] for j < L, 0 up to bN (gather through p.in);
 // B[pen][k] *= bhat[k]; out(pen, k) = A[pen][k] chirp[k] scale (scatter

@@ -260,7 +260,6 @@ void reconstruct_runs(const WavePlan* w, const float2* coeffs, const float* cons
 }  // namespace
 
 size_t wave_saved_elems(const WavePlan* w) {
-  if (w->q != 2) return 0;
   size_t s = 0;
   for (auto& L : w->lv) s += (size_t)(w->batch * L.ml);
   return s;
@@ -306,20 +305,43 @@ double split_q_bytes(long long B, long long ml) { return (16.0 * (double)B + 4.0
 // buffer written by level l of the synthesis walk (l = L-1 .. 0)
 float2* q_target(const QBufs& b, int l) { return l % 2 == 0 ? b.F0 : b.F1; }
 
+// offset of level l's region in `saved`: sum_{j<l} B m_j
+std::vector<long long> saved_offsets(const WavePlan* w) {
+  std::vector<long long> soff(w->levels, 0);
+  long long o = 0;
+  for (int l = 0; l < w->levels; ++l) {
+    soff[l] = o;
+    o += w->batch * w->lv[l].ml;
+  }
+  return soff;
+}
+
+// The analysis walk.  keep: NULL or `saved`, receiving every level's Fourier
+// input ahat_l [B][m_l] (for the mask gradients of the decomposition).
+// rec_saved / gmasks: as the adjoint of a reconstruction, the mask gradient
+// of every level's synthesis from the reconstruction's saved inputs and the
+// gradient arriving at its output (the level's input here).
 void decompose_q(const WavePlan* w, const float2* x, const float* const* masks, float2* coeffs,
-                 void* ws, hipStream_t s, int basis) {
+                 void* ws, hipStream_t s, int basis, float2* keep = nullptr,
+                 const float2* rec_saved = nullptr, float* const* gmasks = nullptr) {
   QBufs b = carve_q(w, ws);
   const long long B = w->batch, m = w->m, q = w->q;
   const int L = w->levels;
   const bool batched = w->chan_dec != nullptr;
-  top_forward(w, x, b.F0, b.FW, m, m, s, basis);
-  float2* cur = b.F0;
+  const std::vector<long long> soff = saved_offsets(w);
+  float2* cur = keep ? keep : b.F0;
+  top_forward(w, x, cur, b.FW, m, m, s, basis);
   for (int l = 0; l < L; ++l) {
     const WaveLevel& V = w->lv[l];
     const long long n = V.ml / q;
     const bool small = batched && l >= w->small_from;
-    float2* next = (batched && l + 1 == L) ? b.ST + w->stage_d1 : (cur == b.F0 ? b.F1 : b.F0);
+    float2* next = (batched && l + 1 == L) ? b.ST + w->stage_d1
+                   : (keep && l + 1 < L) ? keep + soff[l + 1]
+                   : (cur == b.F0 ? b.F1 : b.F0);
     float2* dw = small ? b.ST + w->stage_lvl[l] : b.D;
+    if (gmasks && gmasks[l] && rec_saved)
+      check(launch_unsplit_q_mask_grad(V.sq, B, rec_saved + soff[l], n, rec_saved + soff[l] + B * n,
+                                       (q - 1) * n, masks[l], cur, V.ml, gmasks[l], s));
     {
       TraceScope ts("split_q_kernel", split_q_bytes(B, V.ml), s);
       check(launch_split_q(V.sq, B, cur, V.ml, masks[l], next, n, dw, (q - 1) * n, s));
@@ -341,9 +363,15 @@ void decompose_q(const WavePlan* w, const float2* x, const float* const* masks, 
   }
 }
 
+// The synthesis walk.  dec_saved / gmasks: as the adjoint of a
+// decomposition, the mask gradient of every level's split from the
+// decomposition's saved inputs and the gradients arriving at its outputs
+// (the level's inputs here).
 void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* masks, float2* x,
-                   void* ws, hipStream_t s, int basis) {
+                   void* ws, hipStream_t s, int basis, const float2* dec_saved = nullptr,
+                   float* const* gmasks = nullptr) {
   QBufs b = carve_q(w, ws);
+  const std::vector<long long> soff = saved_offsets(w);
   const long long B = w->batch, m = w->m, q = w->q;
   const int L = w->levels;
   const bool batched = w->chan_rec != nullptr;
@@ -368,6 +396,9 @@ void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* 
         exec_lattice(V.fftW, false, false, false, coeffs + i * m + off, b.D + i * (q - 1) * n, b.FW,
                      n, n, s);
     }
+    if (gmasks && gmasks[l] && dec_saved)
+      check(launch_split_q_mask_grad(V.sq, B, dec_saved + soff[l], V.ml, masks[l], cur, n, dw,
+                                     (q - 1) * n, gmasks[l], s));
     float2* next = q_target(b, l);
     TraceScope ts("unsplit_q_kernel", split_q_bytes(B, V.ml), s);
     check(launch_unsplit_q(V.sq, B, cur, n, dw, (q - 1) * n, masks[l], next, V.ml, s));
@@ -375,13 +406,42 @@ void reconstruct_q(const WavePlan* w, const float2* coeffs, const float* const* 
   }
   top_inverse(w, b.F0, x, b.FW, m, m, s, basis);
 }
+
+// The synthesis with every level's inputs kept in `saved` (channel 0
+// [B][m_l/q], then channels 1 .. q-1 [B][q-1][m_l/q], at offset
+// sum_{j<l} B m_j), for the mask gradients of the reconstruction: one level
+// at a time, no batched channel launch.
+void reconstruct_q_keep(const WavePlan* w, const float2* coeffs, const float* const* masks,
+                        float2* x, float2* saved, void* ws, hipStream_t s) {
+  QBufs b = carve_q(w, ws);
+  const long long B = w->batch, m = w->m, q = w->q;
+  const int L = w->levels;
+  const std::vector<long long> soff = saved_offsets(w);
+  const WaveLevel& VL = w->lv[L - 1];
+  float2* cur = saved + soff[L - 1];
+  exec_lattice(VL.fftN, false, false, false, coeffs + coeff_offset_q(w, L), cur, b.FW, m,
+               VL.ml / q, s);
+  for (int l = L - 1; l >= 0; --l) {
+    const WaveLevel& V = w->lv[l];
+    const long long n = V.ml / q;
+    float2* dw = saved + soff[l] + B * n;
+    const long long off = coeff_offset_q(w, l);
+    for (long long i = 0; i < B; ++i)
+      exec_lattice(V.fftW, false, false, false, coeffs + i * m + off, dw + i * (q - 1) * n, b.FW, n,
+                   n, s);
+    float2* next = l == 0 ? b.F0 : saved + soff[l - 1];
+    TraceScope ts("unsplit_q_kernel", split_q_bytes(B, V.ml), s);
+    check(launch_unsplit_q(V.sq, B, cur, n, dw, (q - 1) * n, masks[l], next, V.ml, s));
+    cur = next;
+  }
+  top_inverse(w, b.F0, x, b.FW, m, m, s, +1);
+}
 }  // namespace
 
 void wave_decompose(const WavePlan* w, const float2* x, const float* const* masks, float2* coeffs,
                     float2* saved, void* ws, hipStream_t s) {
   if (w->q != 2) {
-    if (saved) throw StatusError{E_UNSUPPORTED};
-    decompose_q(w, x, masks, coeffs, ws, s, -1);
+    decompose_q(w, x, masks, coeffs, ws, s, -1, saved);
     return;
   }
   if (!saved) {
@@ -433,8 +493,10 @@ void wave_decompose(const WavePlan* w, const float2* x, const float* const* mask
 void wave_reconstruct(const WavePlan* w, const float2* coeffs, const float* const* masks,
                       float2* x, float2* saved, void* ws, hipStream_t s) {
   if (w->q != 2) {
-    if (saved) throw StatusError{E_UNSUPPORTED};
-    reconstruct_q(w, coeffs, masks, x, ws, s, +1);
+    if (saved)
+      reconstruct_q_keep(w, coeffs, masks, x, saved, ws, s);
+    else
+      reconstruct_q(w, coeffs, masks, x, ws, s, +1);
     return;
   }
   if (!saved) {
@@ -479,8 +541,7 @@ void wave_decompose_backward(const WavePlan* w, const float2* gc, const float2* 
   if (w->q != 2) {
     // the q-channel split's matrix is real, so the unsplit with the same
     // masks is its adjoint and the synthesis is the adjoint of the analysis
-    if (gmasks) throw StatusError{E_UNSUPPORTED};
-    reconstruct_q(w, gc, masks, gx, ws, s, -1);
+    reconstruct_q(w, gc, masks, gx, ws, s, -1, saved, gmasks);
     return;
   }
   Bufs b = carve(w, ws);
@@ -519,8 +580,7 @@ void wave_reconstruct_backward(const WavePlan* w, const float2* gx, const float2
                                const float* const* masks, float2* gc, float* const* gmasks,
                                void* ws, hipStream_t s) {
   if (w->q != 2) {
-    if (gmasks) throw StatusError{E_UNSUPPORTED};
-    decompose_q(w, gx, masks, gc, ws, s, +1);
+    decompose_q(w, gx, masks, gc, ws, s, +1, nullptr, saved, gmasks);
     return;
   }
   Bufs b = carve(w, ws);

@@ -350,6 +350,149 @@ __global__ void __launch_bounds__(256) unsplit_q_kernel(SplitQDesc sd, long long
   }
 }
 
+// d loss / d mask of the q-channel split and synthesis, summed over the batch
+// (one thread per fiber, one writer per mask entry).  Incoming gradients
+// follow the convention G = dL/dRe + i dL/dIm, so dL = sum Re(conj(G) dz);
+// re(g, z) = Re(conj(g) z).  With u_l = a_l / sqrt q, v_l = u_l + sigma [l = 0],
+// c = 2 / v^T v (sigma constant on the fiber, so dc/du_l = -c^2 v_l):
+//  split, x -> dhat (G_0 on dhat_0, G_j on dhat_j), t = sum_l v_l x_l,
+//  Gs = sum_{j>=1} u_j G_j:
+//    dL/du_l = re(G_0, x_l) + c^2 v_l re(Gs, t) - c [l >= 1] re(G_l, t) - c re(Gs, x_l);
+//  synthesis, y -> x (G_l on x_l), tau = sum_{j>=1} u_j y_j, T = sum_l v_l G_l:
+//    dL/du_l = re(G_l, y_0) + c^2 v_l re(T, tau) - c re(G_l, tau) - c [l >= 1] re(T, y_l);
+// and dL/da_l = dL/du_l / sqrt q.
+__device__ __forceinline__ float re_of(float2 g, float2 z) { return g.x * z.x + g.y * z.y; }
+
+template <int Q>
+__global__ void __launch_bounds__(256) split_q_mask_grad_kernel(
+    SplitQDesc sd, long long batch, const float2* __restrict__ ah, long long ah_bs,
+    const float* __restrict__ mask, const float2* __restrict__ g0, long long g0_bs,
+    const float2* __restrict__ gw, long long gw_bs, float* __restrict__ gmask) {
+  constexpr int QM = Q ? Q : kMaxQ;
+  const int q = Q ? Q : sd.q;
+  const long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= sd.mN) return;
+  long long idx[QM];
+  fiber_q<Q>(sd, k, idx);
+  float u[QM], sigma, v0, c;
+  reflector<Q>(sd, mask, idx, u, sigma, v0, c);
+  float acc[QM];
+#pragma unroll
+  for (int l = 0; l < QM; ++l) acc[l] = 0.f;
+  for (long long b = 0; b < batch; ++b) {
+    float2 x[QM], G[QM];
+#pragma unroll
+    for (int l = 0; l < QM; ++l)
+      if (l < q) x[l] = ah[b * ah_bs + idx[l]];
+    G[0] = g0[b * g0_bs + k];
+    const float2* gin = gw + b * gw_bs + k;
+#pragma unroll
+    for (int j = 1; j < QM; ++j)
+      if (j < q) G[j] = gin[(j - 1) * sd.mN];
+    float2 t = make_float2(v0 * x[0].x, v0 * x[0].y);
+    float2 Gs = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int l = 1; l < QM; ++l) {
+      if (l < q) {
+        t = axpby(1.f, t, u[l], x[l]);
+        Gs = axpby(1.f, Gs, u[l], G[l]);
+      }
+    }
+    const float rt = re_of(Gs, t);
+#pragma unroll
+    for (int l = 0; l < QM; ++l) {
+      if (l < q) {
+        const float vl = l ? u[l] : v0;
+        float d = re_of(G[0], x[l]) + c * c * vl * rt - c * re_of(Gs, x[l]);
+        if (l) d -= c * re_of(G[l], t);
+        acc[l] += d;
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < QM; ++l)
+    if (l < q) gmask[idx[l]] = acc[l] * sd.rsq;
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256) unsplit_q_mask_grad_kernel(
+    SplitQDesc sd, long long batch, const float2* __restrict__ d0, long long d0_bs,
+    const float2* __restrict__ dw, long long dw_bs, const float* __restrict__ mask,
+    const float2* __restrict__ g, long long g_bs, float* __restrict__ gmask) {
+  constexpr int QM = Q ? Q : kMaxQ;
+  const int q = Q ? Q : sd.q;
+  const long long k = lfft::dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= sd.mN) return;
+  long long idx[QM];
+  fiber_q<Q>(sd, k, idx);
+  float u[QM], sigma, v0, c;
+  reflector<Q>(sd, mask, idx, u, sigma, v0, c);
+  float acc[QM];
+#pragma unroll
+  for (int l = 0; l < QM; ++l) acc[l] = 0.f;
+  for (long long b = 0; b < batch; ++b) {
+    float2 y[QM], G[QM];
+    y[0] = d0[b * d0_bs + k];
+    const float2* in = dw + b * dw_bs + k;
+#pragma unroll
+    for (int j = 1; j < QM; ++j)
+      if (j < q) y[j] = in[(j - 1) * sd.mN];
+#pragma unroll
+    for (int l = 0; l < QM; ++l)
+      if (l < q) G[l] = g[b * g_bs + idx[l]];
+    float2 tau = make_float2(0.f, 0.f);
+    float2 T = make_float2(v0 * G[0].x, v0 * G[0].y);
+#pragma unroll
+    for (int l = 1; l < QM; ++l) {
+      if (l < q) {
+        tau = axpby(1.f, tau, u[l], y[l]);
+        T = axpby(1.f, T, u[l], G[l]);
+      }
+    }
+    const float rt = re_of(T, tau);
+#pragma unroll
+    for (int l = 0; l < QM; ++l) {
+      if (l < q) {
+        const float vl = l ? u[l] : v0;
+        float d = re_of(G[l], y[0]) + c * c * vl * rt - c * re_of(G[l], tau);
+        if (l) d -= c * re_of(T, y[l]);
+        acc[l] += d;
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < QM; ++l)
+    if (l < q) gmask[idx[l]] = acc[l] * sd.rsq;
+}
+
+template <int Q>
+hipError_t launch_q_mask_grad(const SplitQDesc& sd, bool synthesis, long long batch,
+                              const float2* a, long long a_bs, const float* mask,
+                              const float2* d0, long long d0_bs, const float2* dw,
+                              long long dw_bs, float* gmask, hipStream_t s) {
+  const unsigned grid = (unsigned)((sd.mN + 255) / 256);
+  if (synthesis)
+    hipLaunchKernelGGL(unsplit_q_mask_grad_kernel<Q>, dim3(grid), dim3(256), 0, s, sd, batch, d0,
+                       d0_bs, dw, dw_bs, mask, a, a_bs, gmask);
+  else
+    hipLaunchKernelGGL(split_q_mask_grad_kernel<Q>, dim3(grid), dim3(256), 0, s, sd, batch, a,
+                       a_bs, mask, d0, d0_bs, dw, dw_bs, gmask);
+  return hipGetLastError();
+}
+
+hipError_t dispatch_q_mask_grad(const SplitQDesc& sd, bool synthesis, long long batch,
+                                const float2* a, long long a_bs, const float* mask,
+                                const float2* d0, long long d0_bs, const float2* dw,
+                                long long dw_bs, float* gmask, hipStream_t s) {
+  if (sd.q < 3 || sd.q > kMaxQ) return hipErrorInvalidValue;
+  switch (sd.q) {
+    case 3: return launch_q_mask_grad<3>(sd, synthesis, batch, a, a_bs, mask, d0, d0_bs, dw, dw_bs, gmask, s);
+    case 4: return launch_q_mask_grad<4>(sd, synthesis, batch, a, a_bs, mask, d0, d0_bs, dw, dw_bs, gmask, s);
+    case 8: return launch_q_mask_grad<8>(sd, synthesis, batch, a, a_bs, mask, d0, d0_bs, dw, dw_bs, gmask, s);
+    default: return launch_q_mask_grad<0>(sd, synthesis, batch, a, a_bs, mask, d0, d0_bs, dw, dw_bs, gmask, s);
+  }
+}
+
 template <int Q>
 hipError_t launch_q(const SplitQDesc& sd, bool inverse, long long batch, const float2* a,
                     long long a_bs, const float* mask, const float2* d0c, float2* d0,
@@ -425,6 +568,20 @@ hipError_t launch_unsplit_q(const SplitQDesc& sd, long long batch, const float2*
                             float2* ahat, long long ah_bs, hipStream_t s) {
   return dispatch_q(sd, true, batch, nullptr, ah_bs, mask, d0, nullptr, d0_bs, dw, nullptr, dw_bs,
                     ahat, s);
+}
+
+hipError_t launch_split_q_mask_grad(const SplitQDesc& sd, long long batch, const float2* ahat,
+                                    long long ah_bs, const float* mask, const float2* g0,
+                                    long long g0_bs, const float2* gw, long long gw_bs,
+                                    float* gmask, hipStream_t s) {
+  return dispatch_q_mask_grad(sd, false, batch, ahat, ah_bs, mask, g0, g0_bs, gw, gw_bs, gmask, s);
+}
+
+hipError_t launch_unsplit_q_mask_grad(const SplitQDesc& sd, long long batch, const float2* d0,
+                                      long long d0_bs, const float2* dw, long long dw_bs,
+                                      const float* mask, const float2* g, long long g_bs,
+                                      float* gmask, hipStream_t s) {
+  return dispatch_q_mask_grad(sd, true, batch, g, g_bs, mask, d0, d0_bs, dw, dw_bs, gmask, s);
 }
 
 hipError_t launch_split_chain(int K, const SplitChain& c, long long batch, const float2* ahat,

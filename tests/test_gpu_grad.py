@@ -9,7 +9,7 @@ contribution and their sum are held to the FP32 bound of 1e-5 relative L2."""
 import numpy as np
 import pytest
 
-from oracle import grad as G, lattice as L, wavelet as W
+from oracle import grad as G, lattice as L, wavelet as W, wavelet_q as WQ
 import workloads
 
 torch = pytest.importorskip("torch")
@@ -26,9 +26,12 @@ def gpu_loss(plan, x, masks, target, weights, masks_rec=None):
     from paper_1107_5415_amd import autograd as AG
     c = AG.wavelet_decompose(x, plan, masks)
     loss = torch.zeros((), dtype=torch.float64, device=x.device)
-    for (off, n), w in zip(AG.channel_blocks(plan)[:-1], weights):
+    # every wavelet channel of level l weighted by w_l (the oracle's loss)
+    for (lvl, ch, off, n) in plan.coeff_blocks():
+        if ch == 0:
+            continue
         blk = c[:, off:off + n]
-        loss = loss + w * torch.sum(blk.real.double() ** 2 + blk.imag.double() ** 2)
+        loss = loss + weights[lvl] * torch.sum(blk.real.double() ** 2 + blk.imag.double() ** 2)
     r = AG.wavelet_reconstruct(c, plan, masks if masks_rec is None else masks_rec) - target
     return loss + torch.sum(r.real.double() ** 2 + r.imag.double() ** 2)
 
@@ -39,8 +42,9 @@ def run_case(M, J, levels, B, perturb, seed=5):
     x = workloads.complex_normal(seed, (B, m))
     target = workloads.complex_normal(seed + 1, (B, m))
     rng = np.random.default_rng(seed)
-    masks = [(mk + perturb * rng.standard_normal(mk.shape)).astype(np.float32)
-             for mk in W.default_masks(M, J, levels)]
+    q = abs(L.det(L.as_matrix(J)))
+    base = W.default_masks(M, J, levels) if q == 2 else WQ.default_masks(M, J, levels)
+    masks = [(mk + perturb * rng.standard_normal(mk.shape)).astype(np.float32) for mk in base]
     weights = [1.0] * levels
     plan = lfft.WaveletPlan(M, J, levels, batch=B)
     xd = torch.from_numpy(x).cuda().requires_grad_(True)
@@ -122,6 +126,51 @@ def test_gradients_differentiation_workload():
             return gpu_loss(plan, xd, mm, td, weights).item()
         with torch.no_grad():
             fd = central_difference(f, 0.05)
+        an = float(np.dot(gmask[l].astype(np.float64), u_np.astype(np.float64)))
+        print("level %d mask fd %.6e analytic %.6e" % (l, fd, an), flush=True)
+        assert abs(fd - an) / abs(an) < 2e-3
+
+
+# q = |det J| > 2: the mask gradients go through the reflection rows of the
+# channel matrix (sign(u_0) constant on each fiber)
+QCASES = [
+    (((16, 8), (0, 16)), workloads.J_2I, 2, 2, 0.1),
+    (((27, 9), (0, 9)), ((3, 0), (0, 1)), 2, 2, 0.1),
+    (((8, 4, 0), (0, 8, 4), (0, 0, 8)), ((2, 0, 0), (0, 2, 0), (0, 0, 2)), 1, 2, 0.1),
+    (((256, 64), (0, 256)), workloads.J_2I, 3, 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("M,J,levels,B,perturb", QCASES)
+def test_gradients_vs_oracle_q(M, J, levels, B, perturb):
+    print("case q", M, J, levels, B, flush=True)
+    check_parity(run_case(M, J, levels, B, perturb))
+
+
+def test_gradients_q_finite_differences():
+    """Central differences on the GPU along mask directions of a four-channel
+    pyramid.  The directions leave every fiber's first member unchanged, so
+    sign(u_0) and with it the branch of the reflection stay fixed and the
+    loss is smooth along them."""
+    M, J, levels, B = ((64, 16), (0, 64)), workloads.J_2I, 2, 2
+    print("case q fd", flush=True)
+    r = run_case(M, J, levels, B, 0.1, seed=21)
+    check_parity(r)
+    plan, xd, md, td, weights = r["plan"], r["x"], r["md"], r["target"], r["weights"]
+    gmask = [a + b for a, b in zip(r["gmd"], r["gms"])]
+    rng = np.random.default_rng(22)
+    for l in range(levels):
+        lifts, _ = plan.fiber_map(l)
+        lifts = np.asarray(lifts).reshape(-1, plan.q)
+        u_np = rng.standard_normal(md[l].shape[0]).astype(np.float32)
+        u_np[lifts[:, 0]] = 0.0
+        u = torch.from_numpy(u_np).cuda()
+
+        def f(h):
+            mm = [mk + h * u if j == l else mk for j, mk in enumerate(md)]
+            return gpu_loss(plan, xd, mm, td, weights).item()
+        with torch.no_grad():
+            fd = central_difference(f, 0.02)
         an = float(np.dot(gmask[l].astype(np.float64), u_np.astype(np.float64)))
         print("level %d mask fd %.6e analytic %.6e" % (l, fd, an), flush=True)
         assert abs(fd - an) / abs(an) < 2e-3

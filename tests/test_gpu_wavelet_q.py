@@ -151,14 +151,20 @@ def test_sample_gradients_through_autograd():
     assert rel_l2(x.grad.cpu().numpy(), 2 * x.detach().cpu().numpy()) < 1e-5
 
 
-def test_unsupported_requests():
+def test_mask_gradients_need_saved():
+    """Mask gradients of the q-channel adjoints read the forward call's saved
+    inputs: asking for them without `saved` is an argument error."""
     from paper_1107_5415_amd import lfft
     w = lfft.WaveletPlan(((16, 0), (0, 16)), J2, 1)
     masks = w.dirichlet_masks("cuda")
     x = _dev(workloads.complex_normal(45, 256))
-    with pytest.raises(lfft.LfftError) as e:
-        w.decompose(x, masks, saved=torch.empty(256, dtype=torch.complex64, device="cuda"))
-    assert e.value.code == -5
-    with pytest.raises(lfft.LfftError) as e:
-        w.decompose_backward(x, None, masks, grad_masks=[torch.empty_like(mk) for mk in masks])
-    assert e.value.code == -5
+    for fn in (w.decompose_backward, w.reconstruct_backward):
+        with pytest.raises(lfft.LfftError) as e:
+            fn(x, None, masks, grad_masks=[torch.empty_like(mk) for mk in masks])
+        assert e.value.code == -1
+    # with `saved` the decomposition keeps its Fourier inputs and gives the
+    # same coefficients as without
+    saved = w.new_saved(x.device)
+    assert saved.numel() == 256
+    assert torch.allclose(w.decompose(x, masks, saved=saved), w.decompose(x, masks), rtol=0,
+                          atol=1e-6)

@@ -181,7 +181,7 @@ def test_wavelet_q_levels_and_masks(M, J, levels):
     w = lfft.WaveletPlan(M, J, levels, host_only=True)
     q = abs(L.det(L.as_matrix(J)))
     assert w.q == q
-    assert w.saved_elems() == 0
+    assert w.saved_elems() == sum(w.level_m) * w.batch
     for l, (Ml, Nl) in enumerate(W.level_matrices(M, J, levels)):
         assert tuple(map(tuple, w.level_N[l].tolist())) == Nl
         assert w.level_m[l] == abs(L.det(Ml))
