@@ -55,9 +55,10 @@ extern "C" {
 #define LFFT_E_NOT_INTEGRAL (-3) /* J^{-1} M not integral at some level       */
 #define LFFT_E_OVERFLOW (-4)     /* exact integer work would exceed int64     */
 #define LFFT_E_UNSUPPORTED (-5)  /* d > 4, m >= 2^31, |det J| > 16, or an
-                                    elementary divisor above 2^23 that cannot
-                                    be split into two factors of at most 8192
-                                    (shorter ones run as a chirp-z pass)     */
+                                    elementary divisor above 2^23 that is no
+                                    product of two or three factors of at
+                                    most 8192 (shorter ones run as a chirp-z
+                                    pass)                                    */
 #define LFFT_E_HIP (-6)          /* a HIP call or kernel launch failed        */
 #define LFFT_E_NOMEM (-7)        /* device table allocation failed            */
 #define LFFT_E_STATE (-8)        /* internal consistency check failed, or an

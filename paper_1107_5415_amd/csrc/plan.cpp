@@ -118,6 +118,32 @@ std::vector<int> radices_of(i64 n) {
 
 bool is_pow2(i64 n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Two on-chip digits n = hi * lo (lo the longest divisor of at most
+// kMaxPencil points with hi = n / lo on chip too); 0 if there is none.
+i64 two_digit_lo(i64 n) {
+  for (i64 c = kMaxPencil; c >= 2; --c)
+    if (n % c == 0 && n / c <= kMaxPencil) return c;
+  return 0;
+}
+
+// Three on-chip digits n = n1 * n2 * n3 for cycles beyond two pencils: n3
+// the longest divisor that leaves a two-digit rest, the rest split as
+// above with a high digit of at least 32 points where it is a power of two.
+bool three_digits(i64 n, i64& n1, i64& n2, i64& n3) {
+  for (i64 c = kMaxPencil; c >= 2; --c) {
+    if (n % c != 0) continue;
+    const i64 r = n / c;
+    i64 lo = two_digit_lo(r);
+    if (!lo) continue;
+    if (is_pow2(r) && r / lo < 32 && r >= 32 * 32) lo = r / 32;
+    n1 = r / lo;
+    n2 = lo;
+    n3 = c;
+    return true;
+  }
+  return false;
+}
+
 int ilog2(i64 n) {
   int l = 0;
   while ((i64(1) << l) < n) ++l;
@@ -469,14 +495,22 @@ void build_engine(LatticePlan* p, Engine& E, const Side& in_side, const Side& ou
     pd.scale = (pi == np - 1) ? (float)(1.0 / std::sqrt((double)p->m)) : 1.0f;
     pd.post = R.post ? 1 : 0;
     if (R.post) {
-      // the high digit closes this pass (digit b - 1); the low digit is b
-      const int hi = R.b - 1, lo = R.b;
-      if (dg[hi].part != 1 || lo >= D || dg[lo].part != 2) throw StatusError{E_STATE};
-      i64 N = dg[hi].n * dg[lo].n;
+      // the high digit closes this pass (digit b - 1); the still untransformed
+      // lower digits of its axis follow it (digits b .. e, the last one the
+      // low digit): twiddle exponent k_hi * (their combined input index)
+      // modulo the product of the axis's digits from the high one on
+      const int hi = R.b - 1;
+      if (dg[hi].part != 1 && dg[hi].part != 4) throw StatusError{E_STATE};
+      int e = R.b;
+      while (e < D && dg[e].part == 4 && dg[e].axis == dg[hi].axis) ++e;
+      if (e >= D || dg[e].part != 2 || dg[e].axis != dg[hi].axis) throw StatusError{E_STATE};
+      const i64 lo_n = range_count(dg, R.b, e + 1);
+      const i64 N = dg[hi].n * lo_n;
+      if (N >= (i64(1) << 31)) throw StatusError{E_UNSUPPORTED};
       pd.postN = (int)N;
       pd.post_lmod = (int)dg[hi].n;
-      pd.lo_n = (int)dg[lo].n;
-      pd.lo_div = (int)range_count(dg, lo + 1, D);
+      pd.lo_n = (int)lo_n;
+      pd.lo_div = (int)range_count(dg, e + 1, D);
       auto pr = tw.twolevel(N);
       pd.tw_hi = pr.first;
       pd.tw_lo = pr.second;
@@ -591,14 +625,19 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
           if (n > kMaxTile) throw StatusError{E_UNSUPPORTED};
           p->digits.push_back(Digit{j, n, 0, 1, 1});
         } else {
-          i64 lo = 0;
-          for (i64 c = kMaxPencil; c >= 2; --c)
-            if (n % c == 0 && n / c <= kMaxPencil) {
-              lo = c;
-              break;
-            }
+          i64 lo = two_digit_lo(n);
           if (!lo) {
-            // no split into two on-chip digits: the whole axis by chirp-z
+            // beyond two pencils: three on-chip digits with two four-step
+            // twiddles (input index n1-digit * n2 n3 + n2-digit * n3 +
+            // n3-digit, output index k1 + n1 k2 + n1 n2 k3)
+            i64 n1 = 0, n2 = 0, n3 = 0;
+            if (three_digits(n, n1, n2, n3)) {
+              p->digits.push_back(Digit{j, n1, 1, n2 * n3, 1});
+              p->digits.push_back(Digit{j, n2, 4, n3, n1});
+              p->digits.push_back(Digit{j, n3, 2, 1, n1 * n2});
+              continue;
+            }
+            // no split into on-chip digits: the whole axis by chirp-z
             if (n > kMaxBlueAxis) throw StatusError{E_UNSUPPORTED};
             p->digits.push_back(Digit{j, n, 3, 1, 1});
             continue;
@@ -648,7 +687,21 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
     } else {
       int i = Dg - 1;
       while (i >= 0) {
-        if (p->digits[i].part == 2) {
+        if (p->digits[i].part == 2 && i >= 2 && p->digits[i - 1].part == 4) {
+          // an axis split in three: high digit (with the whole axes before
+          // it that fit one pencil), then the middle, then the low digit,
+          // each of the first two followed by its four-step twiddle
+          int a = i - 2;
+          i64 prod = p->digits[a].n;
+          while (a - 1 >= 0 && p->digits[a - 1].part == 0 && prod * p->digits[a - 1].n <= kMaxPencil) {
+            --a;
+            prod *= p->digits[a].n;
+          }
+          p->ranges.push_back(PassRange{a, i - 1, true, p->digits[i].axis});
+          p->ranges.push_back(PassRange{i - 1, i, true, p->digits[i].axis});
+          p->ranges.push_back(PassRange{i, i + 1, false, 0});
+          i = a - 1;
+        } else if (p->digits[i].part == 2) {
           // the high digit closes a pass that also takes the whole axes
           // before it while they fit one pencil (no pass over a short axis
           // alone); its four-step twiddle follows the pass

@@ -47,7 +47,8 @@ struct Digit {
   int axis;                 // non-trivial grid axis
   i64 n;                    // digit length
   int part;                 // 0 whole axis, 1 high digit, 2 low digit, 3 whole axis
-                            // by chirp-z (a prime factor too large for one pencil)
+                            // by chirp-z (a prime factor too large for one pencil),
+                            // 4 middle digit of an axis split in three
   i64 w_in;                 // grid-coordinate weight on the input side
   i64 w_out;                // grid-coordinate weight on the output side
 };

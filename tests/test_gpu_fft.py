@@ -174,6 +174,28 @@ def test_large_forward_inverse_full_size():
     assert rel_l2(Z, dft.lattice_dft_hnf(M, z, inverse=True)) < TOL
 
 
+@pytest.mark.parametrize("name,M", [
+    ("d1_2^27", ((1 << 27,),)),
+    ("d1_3x2^25", ((3 << 25,),)),
+    ("sheared_cyclic_2^27", ((2, 1), (0, 1 << 26))),
+])
+def test_cycles_split_in_three(name, M):
+    """Cycles longer than two on-chip pencils (above 2^26 points) run as
+    three passes with two four-step twiddles; forward against the Hermite
+    FP64 FFT and inverse round trip."""
+    lfft = _lfft()
+    m = abs(L.det(M))
+    print("case", name, "m", m, flush=True)
+    plan = lfft.LatticePlan(M)
+    assert plan.query()["passes"] == 3
+    x = workloads.complex_normal(61, m)
+    xd = _dev(x)
+    X = plan.forward(xd)
+    assert rel_l2(X.cpu().numpy(), dft.lattice_dft_hnf(M, x)) < TOL
+    back = plan.inverse(X).cpu().numpy()
+    assert rel_l2(back, x) < 2 * TOL
+
+
 def test_d3_full_size_forward():
     lfft = _lfft()
     cfg = workloads.CONFIGS["d3"]

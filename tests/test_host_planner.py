@@ -515,3 +515,17 @@ def test_short_axis_split_bounds():
     q = lfft.LatticePlan(((16, 0, 0), (0, 4096, 0), (0, 0, 4096)), host_only=True).query()
     assert tuple(int(e) for e in q["eps"]) == (16, 4096, 4096)
     assert q["passes"] == 3
+
+
+@pytest.mark.parametrize("M,eps", [
+    (((1 << 27,),), (1 << 27,)),
+    (((3 << 25,),), (3 << 25,)),
+    (((1 << 30,),), (1 << 30,)),
+    (((2, 0), (0, 1 << 27)), (2, 1 << 27)),
+])
+def test_cycles_beyond_two_pencils_plan_in_three_passes(M, eps):
+    """A cycle longer than 8192^2 points with three on-chip factors splits
+    into three digits (two four-step twiddles): three passes."""
+    q = lfft.LatticePlan(M, host_only=True).query()
+    assert tuple(int(e) for e in q["eps"] if e > 1) == eps
+    assert q["passes"] == 3
