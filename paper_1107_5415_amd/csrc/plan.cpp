@@ -126,22 +126,40 @@ i64 two_digit_lo(i64 n) {
   return 0;
 }
 
-// Three on-chip digits n = n1 * n2 * n3 for cycles beyond two pencils: n3
-// the longest divisor that leaves a two-digit rest, the rest split as
-// above with a high digit of at least 32 points where it is a power of two.
+// Three on-chip digits n = n1 * n2 * n3 for cycles beyond two pencils.  The
+// natural-order tables of the first pass span n2 n3 points and those of the
+// last pass n1 n2, so the choice keeps both within 2^20 entries where it can
+// and then takes the longest shortest digit (pencils of the register-resident
+// kernels), then the longest last digit.
 bool three_digits(i64 n, i64& n1, i64& n2, i64& n3) {
-  for (i64 c = kMaxPencil; c >= 2; --c) {
-    if (n % c != 0) continue;
-    const i64 r = n / c;
-    i64 lo = two_digit_lo(r);
-    if (!lo) continue;
-    if (is_pow2(r) && r / lo < 32 && r >= 32 * 32) lo = r / 32;
-    n1 = r / lo;
-    n2 = lo;
-    n3 = c;
-    return true;
+  std::vector<i64> dv;
+  for (i64 c = 2; c <= kMaxPencil; ++c)
+    if (n % c == 0) dv.push_back(c);
+  bool found = false;
+  int best_bucket = 0;
+  i64 best_min = 0, best_last = 0;
+  for (i64 c : dv) {
+    for (i64 a : dv) {
+      if ((n / c) % a != 0) continue;
+      const i64 b = n / c / a;
+      if (b < 2 || b > kMaxPencil) continue;
+      const i64 table = std::max(a * b, b * c);
+      int bucket = 0;
+      while ((i64(1) << (20 + bucket)) < table) ++bucket;
+      const i64 mn = std::min(a, std::min(b, c));
+      if (!found || bucket < best_bucket ||
+          (bucket == best_bucket && (mn > best_min || (mn == best_min && c > best_last)))) {
+        found = true;
+        best_bucket = bucket;
+        best_min = mn;
+        best_last = c;
+        n1 = a;
+        n2 = b;
+        n3 = c;
+      }
+    }
   }
-  return false;
+  return found;
 }
 
 int ilog2(i64 n) {

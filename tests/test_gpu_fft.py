@@ -177,6 +177,7 @@ def test_large_forward_inverse_full_size():
 @pytest.mark.parametrize("name,M", [
     ("d1_2^27", ((1 << 27,),)),
     ("d1_3x2^25", ((3 << 25,),)),
+    ("d1_2^28", ((1 << 28,),)),
     ("sheared_cyclic_2^27", ((2, 1), (0, 1 << 26))),
 ])
 def test_cycles_split_in_three(name, M):
@@ -194,6 +195,42 @@ def test_cycles_split_in_three(name, M):
     assert rel_l2(X.cpu().numpy(), dft.lattice_dft_hnf(M, x)) < TOL
     back = plan.inverse(X).cpu().numpy()
     assert rel_l2(back, x) < 2 * TOL
+
+
+def test_cycle_of_2_30_points():
+    """The longest cycle the planner takes (three digits of 1024): exact bins
+    of a sparse signal at sampled frequencies (its unitary DFT in closed form,
+    phases reduced mod m in integers), Parseval and the round trip on a dense
+    one."""
+    lfft = _lfft()
+    m = 1 << 30
+    plan = lfft.LatticePlan(((m,),))
+    assert plan.query()["passes"] == 3
+    rng = np.random.default_rng(30)
+    k = rng.choice(m, 8, replace=False).astype(np.int64)
+    a = workloads.complex_normal(31, 8).astype(np.complex128)
+    print("case 2^30 sparse", flush=True)
+    xs = torch.zeros(m, dtype=torch.complex64, device="cuda")
+    xs[torch.from_numpy(k).cuda()] = torch.from_numpy(a.astype(np.complex64)).cuda()
+    X = plan.forward(xs)
+    del xs
+    h = np.concatenate([rng.integers(0, m, 4096), [0, 1, m - 1]]).astype(np.int64)
+    got = X[torch.from_numpy(h).cuda()].cpu().numpy().astype(np.complex128)
+    del X
+    r = (h[:, None] * k[None, :]) % m
+    want = (a[None, :] * np.exp(-2j * np.pi * r / m)).sum(1) / np.sqrt(m)
+    assert rel_l2(got, want) < TOL
+    print("case 2^30 dense", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(32)
+    x = torch.randn(m, dtype=torch.complex64, device="cuda", generator=g)
+    X = plan.forward(x)
+    nx = torch.linalg.vector_norm(x.to(torch.complex128)).item()
+    nX = torch.linalg.vector_norm(X.to(torch.complex128)).item()
+    assert abs(nX / nx - 1) < 1e-5
+    back = plan.inverse(X)
+    del X
+    err = torch.linalg.vector_norm((back - x).to(torch.complex128)).item() / nx
+    assert err < 2 * TOL
 
 
 def test_d3_full_size_forward():
