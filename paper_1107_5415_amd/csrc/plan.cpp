@@ -784,6 +784,16 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       p->ranges = ranges;
       p->has_inv_rev = true;
     }
+    if (p->Si_aligned && !p->Sf_aligned && !posts && p->ranges.size() >= 2) {
+      // the mirror case: a first pass over rows of unaligned samples would
+      // gather scattered elements, so the forward runs on the inverse basis
+      // with the rows pass last, writing the aligned frequency rows
+      const auto ranges = p->ranges;
+      std::reverse(p->ranges.begin(), p->ranges.end());
+      build_engine(p, p->fwd_rev, iff, is, -1, tw);
+      p->ranges = ranges;
+      p->has_fwd_rev = true;
+    }
   } catch (const StatusError&) {
     delete p;
     throw;
@@ -809,6 +819,7 @@ void upload_plan(LatticePlan* p) {
   patch_engine(p->inv_grid, base);
   patch_engine(p->inv_nat, base);
   if (p->has_inv_rev) patch_engine(p->inv_rev, base);
+  if (p->has_fwd_rev) patch_engine(p->fwd_rev, base);
 }
 
 void free_plan(LatticePlan* p) {
@@ -985,9 +996,9 @@ void exec_chirp_z(const LatticePlan* p, const PassDesc& pd, const float2* src, f
 void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_grid, const void* in,
                   void* out, void* ws, long long bin, long long bout, hipStream_t s,
                   float scale_mul) {
-  const Engine& E = !inverse ? p->fwd
-                             : ((in_grid || out_grid) ? p->inv_grid
-                                                      : (p->has_inv_rev ? p->inv_rev : p->inv_nat));
+  const bool nat = !in_grid && !out_grid;
+  const Engine& E = !inverse ? ((nat && p->has_fwd_rev) ? p->fwd_rev : p->fwd)
+                             : (!nat ? p->inv_grid : (p->has_inv_rev ? p->inv_rev : p->inv_nat));
   const int np = (int)E.passes.size();
   for (int i = 0; i < np; ++i) {
     PassDesc pd = E.passes[i];

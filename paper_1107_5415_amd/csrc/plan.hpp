@@ -101,6 +101,12 @@ struct LatticePlan {
   // by exec_lattice and by the batched launch
   Engine inv_rev;
   bool has_inv_rev = false;
+  // natural -> natural forward on the inverse basis with the passes in
+  // reverse order (built when only the inverse basis is aligned and no axis
+  // is split four-step): the last pass writes the frequency rows that basis
+  // aligns; used by exec_lattice
+  Engine fwd_rev;
+  bool has_fwd_rev = false;
   Blob blob;
   void* dtab = nullptr;     // device copy of blob
   size_t ws_elems = 0;      // workspace (complex64 elements) per call

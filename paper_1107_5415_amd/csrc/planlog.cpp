@@ -62,7 +62,7 @@ void log_lattice_plan(const LatticePlan* p, const char* label) {
                (int)p->fwd.passes.size(), p->Sf_aligned ? " forward-aligned" : "",
                p->Si_aligned ? " inverse-aligned" : "",
                (p->flags & kPlanSplitBf16) ? " split-bf16" : "");
-  log_engine(p, p->fwd, "forward");
+  log_engine(p, p->has_fwd_rev ? p->fwd_rev : p->fwd, "forward");
   log_engine(p, p->has_inv_rev ? p->inv_rev : p->inv_nat, "inverse");
 }
 

@@ -16,6 +16,8 @@ cfg = workloads.CONFIGS["large"]
 lfft.LatticePlan(cfg["M"], host_only=True)
 lfft.WaveletPlan(cfg["M"], cfg["J"], 3, host_only=True)
 lfft.BatchPlan(workloads.batched_matrices(count=8), host_only=True)
+M = cfg["M"]
+lfft.LatticePlan(tuple(tuple(M[j][i] for j in range(2)) for i in range(2)), host_only=True)
 """ % ROOT
 
 
@@ -45,6 +47,12 @@ def test_log_prints_the_schedule():
                for l in lines), err
     assert sum("  level " in l for l in lines) == 3
     assert any(l.startswith("lfft: batch lattices=8") for l in lines), err
+    # the transposed matrix aligns only its inverse basis: its forward takes
+    # the column tiles first and ends with rows onto the natural frequencies
+    i = next(k for k, l in enumerate(lines) if "basis inverse-aligned" in l
+             and "forward-aligned" not in l)
+    assert "forward  pass 1/2 fft_stream_kernel<2048, 8, true, false, 2, 0>" in lines[i + 1], err
+    assert "forward  pass 2/2 fft_stream_kernel<8192, 1, false, false, 0, 2>" in lines[i + 2], err
 
 
 def test_log_is_silent_by_default():
