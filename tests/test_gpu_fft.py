@@ -233,6 +233,52 @@ def test_cycle_of_2_30_points():
     assert err < 2 * TOL
 
 
+def _random_lattice(seed):
+    """Seeded random regular matrices: d = 2, 3, 4 in turn, entries and
+    determinant bounds that give m from a few hundred to 2^18 points, every
+    shape (Hermite form with any diagonal, Smith grids of one to four axes,
+    either basis aligned or neither)."""
+    rng = np.random.default_rng(1000 + seed)
+    d = 2 + seed % 3
+    if seed >= 36:
+        # several elementary divisors: U1 diag(e) U2 with random unimodular
+        # U1, U2 (products of integer row and column additions)
+        while True:
+            base = rng.choice([1, 2, 3, 4, 6, 8, 12, 16, 32, 64, 128], size=d)
+            e = np.cumprod(base).astype(np.int64)   # e_1 | e_2 | ... | e_d
+            if (1 << 12) <= int(np.prod(e)) <= (1 << 20):
+                break
+        A = np.diag(e[::-1])
+        for _ in range(2 * d):
+            i, j = rng.choice(d, 2, replace=False)
+            A[i] += int(rng.integers(-2, 3)) * A[j]
+            i, j = rng.choice(d, 2, replace=False)
+            A[:, i] += int(rng.integers(-2, 3)) * A[:, j]
+        return tuple(tuple(int(v) for v in row) for row in A)
+    lo, hi, md = {2: (-600, 601, 1 << 18), 3: (-60, 61, 1 << 18), 4: (-12, 13, 1 << 17)}[d]
+    while True:
+        M = workloads.random_regular_matrix(rng, d, lo=lo, hi=hi, max_det=md)
+        if abs(L.det(M)) >= 256:
+            return M
+
+
+@pytest.mark.parametrize("seed", range(48))
+def test_random_lattices(seed):
+    """Forward and inverse, natural order, batch 2, on random lattices."""
+    lfft = _lfft()
+    M = _random_lattice(seed)
+    m = abs(L.det(M))
+    print("case seed", seed, "M", M, "m", m, flush=True)
+    plan = lfft.LatticePlan(M, batch=2)
+    x = workloads.complex_normal(70 + seed, (2, m))
+    X = plan.forward(_dev(x)).cpu().numpy()
+    for b in range(2):
+        assert rel_l2(X[b], oracle_fft(M, x[b])) < TOL
+    Y = plan.inverse(_dev(x)).cpu().numpy()
+    for b in range(2):
+        assert rel_l2(Y[b], oracle_fft(M, x[b], inverse=True)) < TOL
+
+
 def test_d3_full_size_forward():
     lfft = _lfft()
     cfg = workloads.CONFIGS["d3"]
