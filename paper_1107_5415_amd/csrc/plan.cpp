@@ -784,10 +784,11 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       p->ranges = ranges;
       p->has_inv_rev = true;
     }
-    if (p->Si_aligned && !p->Sf_aligned && !posts && p->ranges.size() >= 2) {
+    if (p->Si_aligned && !p->Sf_aligned && !posts && p->ranges.size() >= 2 && tile_lg == 0) {
       // the mirror case: a first pass over rows of unaligned samples would
       // gather scattered elements, so the forward runs on the inverse basis
-      // with the rows pass last, writing the aligned frequency rows
+      // with the rows pass last, writing the aligned frequency rows (the
+      // fixed-tile schedules keep their forward order)
       const auto ranges = p->ranges;
       std::reverse(p->ranges.begin(), p->ranges.end());
       build_engine(p, p->fwd_rev, iff, is, -1, tw);

@@ -102,9 +102,9 @@ struct LatticePlan {
   Engine inv_rev;
   bool has_inv_rev = false;
   // natural -> natural forward on the inverse basis with the passes in
-  // reverse order (built when only the inverse basis is aligned and no axis
-  // is split four-step): the last pass writes the frequency rows that basis
-  // aligns; used by exec_lattice
+  // reverse order (built for the default schedule when only the inverse
+  // basis is aligned and no axis is split four-step): the last pass writes
+  // the frequency rows that basis aligns; used by exec_lattice
   Engine fwd_rev;
   bool has_fwd_rev = false;
   Blob blob;

@@ -34,6 +34,8 @@ CASES = [
     ("d3_small", ((16, 4, 0), (0, 16, 4), (0, 0, 16)), 2),
     ("quincunx_level", ((2048, 3072), (2048, -1024)), 1),
     ("ragged_cols", ((64, 0), (0, 64)), 3),
+    # only the inverse basis aligned (lower triangular)
+    ("lower_triangular_2^14", ((128, 0), (32, 128)), 2),
 ]
 
 
