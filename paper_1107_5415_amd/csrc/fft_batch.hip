@@ -13,6 +13,8 @@
 // are empty.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fast_tile.hpp"
 #include "kernels.hpp"
 
@@ -85,15 +87,15 @@ __global__ void __launch_bounds__(64) batch_clear_kernel(int* heads, int n) {
   if (i < n) heads[kHeadStride * i] = 0;
 }
 
-bool g_attr = false;
+std::atomic<bool> g_attr{false};
 
 hipError_t set_attr() {
-  if (g_attr) return hipSuccess;
+  if (g_attr.load(std::memory_order_acquire)) return hipSuccess;
   // the dynamic size requested exactly: the kernel also has static LDS
   hipError_t e = hipFuncSetAttribute((const void*)fft_batch_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)batch_lds_bytes(1 << 13));
-  if (e == hipSuccess) g_attr = true;
+  if (e == hipSuccess) g_attr.store(true, std::memory_order_release);
   return e;
 }
 

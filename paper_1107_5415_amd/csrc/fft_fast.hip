@@ -14,6 +14,8 @@
 // group addition of one constant.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fast_tile.hpp"
 #include "kernels.hpp"
 #include "ktrace.hpp"
@@ -33,12 +35,13 @@ __global__ void __launch_bounds__(1024) fft_fast_kernel(PassDesc p, const float2
 template <int P, bool COLS, bool SPLIT, int MIN, int MOUT>
 hipError_t launch_t(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
   auto k = fft_fast_kernel<P, COLS, SPLIT, MIN, MOUT>;
-  static bool attr = false;
-  if (!attr) {
+  // set once; threads that race here all write the same attribute
+  static std::atomic<bool> attr{false};
+  if (!attr.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
+    attr.store(true, std::memory_order_release);
   }
   const long long npen = p.batch * (long long)p.O * p.S;
   const long long tiles = (npen + p.W - 1) / p.W;

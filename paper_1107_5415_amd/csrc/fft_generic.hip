@@ -10,6 +10,8 @@
 // basis (Section 3), so neither order is ever materialised separately.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fft_common.hpp"
 #include "kernels.hpp"
 
@@ -180,12 +182,12 @@ hipError_t launch_pass(const PassDesc& p, const float2* in, float2* out, hipStre
   if (p.kind == 3) return launch_mfma_pass(p, in, out, s);
   if (p.kind == 2) return launch_stream_pass(p, in, out, s);
   if (p.kind == 1) return launch_fast_pass(p, in, out, s);
-  static bool attr = false;
-  if (!attr) {
+  static std::atomic<bool> attr{false};
+  if (!attr.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute((const void*)pass_generic_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
+    attr.store(true, std::memory_order_release);
   }
   const long long npen = p.batch * (long long)p.O * p.S;
   const long long tiles = (npen + p.TP - 1) / p.TP;

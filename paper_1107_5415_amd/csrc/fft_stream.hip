@@ -12,6 +12,8 @@
 // global access is a 32-bit offset from a uniform base.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fft_common.hpp"
 #include "kernels.hpp"
 #include "ktrace.hpp"
@@ -391,7 +393,9 @@ __global__ void __launch_bounds__(W * L / kP, (COLS ? kColsWgPerCu : kRowsWgPerC
   }
 }
 
-int g_cus = 0;
+// compute units of the device and, per kernel, workgroups per CU: found on
+// first use; threads that race here all store the same values
+std::atomic<int> g_cus{0};
 
 template <int L, int W, bool COLS, bool SPLIT, int MIN, int MOUT>
 hipError_t launch_t(const PassDesc& p, const float2* in, float2* out, hipStream_t s) {
@@ -399,7 +403,8 @@ hipError_t launch_t(const PassDesc& p, const float2* in, float2* out, hipStream_
   constexpr int NT = W * L / kP;
   constexpr int tile = W * L;
   constexpr size_t lds = (size_t)(tile + tile / 16 + 1) * (SPLIT ? sizeof(float) : sizeof(float2));
-  static int wgs_per_cu = 0;
+  static std::atomic<int> wgs_cache{0};
+  int wgs_per_cu = wgs_cache.load(std::memory_order_acquire);
   if (!wgs_per_cu) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024);
@@ -408,17 +413,20 @@ hipError_t launch_t(const PassDesc& p, const float2* in, float2* out, hipStream_
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds);
     if (e != hipSuccess) return e;
     wgs_per_cu = nb > 0 ? nb : 1;
+    wgs_cache.store(wgs_per_cu, std::memory_order_release);
   }
-  if (!g_cus) {
+  int cus = g_cus.load(std::memory_order_acquire);
+  if (!cus) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
+    g_cus.store(cus, std::memory_order_release);
   }
   const long long npen = p.batch * (long long)p.O * p.S;
   const long long ntiles = (npen + W - 1) / W;
-  long long grid = (long long)g_cus * wgs_per_cu;
+  long long grid = (long long)cus * wgs_per_cu;
   if (grid > ntiles) grid = ntiles;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, p, in, out);
   return hipGetLastError();
