@@ -54,6 +54,11 @@ struct PassDesc {
   StageDesc st[kMaxStages];
   int sign;                   // -1 forward, +1 inverse
   float scale;                // applied when storing
+  // streaming kernel, last pass of a natural-order transform whose rows
+  // pencils write whole aligned rows of the caller's output: stores marked
+  // non-temporal, so that they do not evict the input and the intermediate
+  // grid from the caches
+  int stream_out;
   // four-step twiddle after the stages: x = ((l mod post_lmod) * lo) mod
   // postN with lo = (s / lo_div) % lo_n, factor exp(sign 2 pi i x / postN)
   // from the two-level table tw_hi[x >> 12] * tw_lo[x & 4095]; the high digit

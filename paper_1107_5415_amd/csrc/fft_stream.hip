@@ -353,7 +353,17 @@ __device__ __forceinline__ void store_tile(const float2* v, const PassDesc& p,
         x.x *= p.scale;
         x.y *= p.scale;
       }
-      base[(unsigned)off] = x;
+      if constexpr (MOUT == MAP_NATURAL && !COLS) {
+        if (p.stream_out) {
+          typedef float nt_f2 __attribute__((ext_vector_type(2)));
+          const nt_f2 v2 = {x.x, x.y};
+          __builtin_nontemporal_store(v2, reinterpret_cast<nt_f2*>(base + (unsigned)off));
+        } else {
+          base[(unsigned)off] = x;
+        }
+      } else {
+        base[(unsigned)off] = x;
+      }
     });
   }
 }

@@ -795,6 +795,13 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       p->ranges = ranges;
       p->has_fwd_rev = true;
     }
+    // the reversed engines end with a rows pass onto the aligned side: whole
+    // rows of the output, written once and not read again by the call
+    for (Engine* E : {p->has_inv_rev ? &p->inv_rev : nullptr, p->has_fwd_rev ? &p->fwd_rev : nullptr}) {
+      if (!E || E->passes.empty()) continue;
+      PassDesc& last = E->passes.back();
+      if (last.kind == 2 && last.S == 1) last.stream_out = 1;
+    }
   } catch (const StatusError&) {
     delete p;
     throw;
@@ -1015,6 +1022,7 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
       pd.out = out_grid ? E.out_grid : E.out_nat;
       pd.out.bstride = bout;
       pd.scale *= scale_mul;
+      if (out_grid) pd.stream_out = 0;
     }
     const double fft_bytes = 16.0 * (double)p->batch * (double)p->m;
     if (pd.kind == 4) {

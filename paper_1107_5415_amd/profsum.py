@@ -1,9 +1,9 @@
 """Summaries of rocprofv3 CSV output for the committed profiles.
 
   python -m paper_1107_5415_amd.profsum stats STATS_CSV --cmd "..." --out FILE
-      [--trace TRACE_CSV --tail-kernel NAME --tail-n N]
+      [--trace TRACE_CSV --tail-kernel NAME --tail-n N [--tail-kernel ... --tail-n ...]]
       per-kernel calls / total / average duration from --kernel-trace --stats,
-      and the average of the last N dispatches of one kernel
+      and the average of the last N dispatches of each named kernel
   python -m paper_1107_5415_amd.profsum sq CSV [CSV ...] --write-csv WRITE_CSV --copy-kib KIB
       --cmd "..." [--cmd "..."] --out FILE
       per-kernel averages per dispatch of the SQ counters in the CSVs, with
@@ -34,7 +34,7 @@ def _short(name):
         "(lfft::PassDesc, HIP_vector_type<float, 2u> const*, HIP_vector_type<float, 2u>*)", "")
 
 
-def stats(path, cmd, out, trace=None, tail_kernel=None, tail_n=0):
+def stats(path, cmd, out, trace=None, tails=()):
     rows = list(csv.DictReader(open(path)))
     lines = ["# rocprofv3 --kernel-trace --stats summary", "# command: " + cmd, "",
              "%-72s %7s %12s %11s %6s" % ("kernel", "calls", "total_us", "avg_us", "pct")]
@@ -42,14 +42,17 @@ def stats(path, cmd, out, trace=None, tail_kernel=None, tail_n=0):
         lines.append("%-72s %7d %12.1f %11.2f %6.2f" % (
             _short(r["Name"])[:72], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
             float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
-    if trace and tail_kernel and tail_n:
-        # the last tail_n dispatches of one kernel (the benchmark's traced
+    if trace and tails:
+        # the last tail_n dispatches of each kernel (the benchmark's traced
         # pass runs last), from the per-dispatch kernel trace
-        tr = [r for r in csv.DictReader(open(trace)) if tail_kernel in r["Kernel_Name"]]
-        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
-        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr[-tail_n:]]
-        lines += ["", "# last %d dispatches of %s (the traced pass): avg_us %.2f, min %.2f, max %.2f"
-                  % (len(d), tail_kernel, statistics.mean(d), min(d), max(d))]
+        rows_tr = list(csv.DictReader(open(trace)))
+        lines.append("")
+        for tail_kernel, tail_n in tails:
+            tr = [r for r in rows_tr if tail_kernel in r["Kernel_Name"]]
+            tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr[-tail_n:]]
+            lines.append("# last %d dispatches of %s (the traced pass): avg_us %.2f, min %.2f, max %.2f"
+                         % (len(d), tail_kernel, statistics.mean(d), min(d), max(d)))
     open(out, "w").write("\n".join(lines) + "\n")
 
 
@@ -187,8 +190,8 @@ def main():
     s.add_argument("--cmd", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--trace", default=None)
-    s.add_argument("--tail-kernel", default=None)
-    s.add_argument("--tail-n", type=int, default=0)
+    s.add_argument("--tail-kernel", action="append", default=[])
+    s.add_argument("--tail-n", type=int, action="append", default=[])
     q = sub.add_parser("sq")
     q.add_argument("csvs", nargs="+")
     q.add_argument("--write-csv", required=True)
@@ -208,7 +211,9 @@ def main():
     t.add_argument("--alg-per-write", type=float, default=None)
     a = ap.parse_args()
     if a.what == "stats":
-        stats(a.csv, a.cmd, a.out, a.trace, a.tail_kernel, a.tail_n)
+        if len(a.tail_kernel) != len(a.tail_n):
+            raise SystemExit("--tail-kernel and --tail-n come in pairs")
+        stats(a.csv, a.cmd, a.out, a.trace, list(zip(a.tail_kernel, a.tail_n)))
     elif a.what == "sq":
         sq(a.csvs, a.write_csv, a.copy_kib, a.cmd, a.out)
     elif a.what == "traffic":
