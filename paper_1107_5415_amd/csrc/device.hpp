@@ -59,6 +59,10 @@ struct PassDesc {
   // non-temporal, so that they do not evict the input and the intermediate
   // grid from the caches
   int stream_out;
+  // streaming kernel, first pass reading whole aligned rows of the caller's
+  // natural-order input (read once by the call): loads marked non-temporal,
+  // so that the intermediate grid stays in the caches for the next pass
+  int stream_in;
   // four-step twiddle after the stages: x = ((l mod post_lmod) * lo) mod
   // postN with lo = (s / lo_div) % lo_n, factor exp(sign 2 pi i x / postN)
   // from the two-level table tw_hi[x >> 12] * tw_lo[x & 4095]; the high digit

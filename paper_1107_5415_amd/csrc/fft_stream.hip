@@ -171,7 +171,18 @@ __device__ __forceinline__ void load_tile(float2* v, const PassDesc& p, const fl
   for (int q = 0; q < kP / R; ++q) {
     const int j = jt + TPP * q;
     side_positions<MIN, R>(A, p.in, p.S, j, L / R,
-                           [&](int i, int off) { v[q * R + i] = A.base[(unsigned)off]; });
+                           [&](int i, int off) {
+                             if constexpr (MIN == MAP_NATURAL && !COLS) {
+                               if (p.stream_in) {
+                                 typedef float nt_f2 __attribute__((ext_vector_type(2)));
+                                 const nt_f2 t = __builtin_nontemporal_load(
+                                     reinterpret_cast<const nt_f2*>(A.base + (unsigned)off));
+                                 v[q * R + i] = make_float2(t.x, t.y);
+                                 return;
+                               }
+                             }
+                             v[q * R + i] = A.base[(unsigned)off];
+                           });
   }
 }
 

@@ -802,6 +802,13 @@ LatticePlan* build_lattice_plan(int d, const i64* Mrm, i64 batch, uint32_t flags
       PassDesc& last = E->passes.back();
       if (last.kind == 2 && last.S == 1) last.stream_out = 1;
     }
+    // the engines in natural order start with a rows pass over the input
+    // side that their basis aligns: whole rows of the input, read once
+    for (Engine* E : {p->Sf_aligned ? &p->fwd : nullptr, p->Si_aligned ? &p->inv_nat : nullptr}) {
+      if (!E || E->passes.empty()) continue;
+      PassDesc& first = E->passes.front();
+      if (first.kind == 2 && first.S == 1) first.stream_in = 1;
+    }
   } catch (const StatusError&) {
     delete p;
     throw;
@@ -1017,6 +1024,7 @@ void exec_lattice(const LatticePlan* p, bool inverse, bool in_grid, bool out_gri
     if (i == 0) {
       pd.in = in_grid ? E.in_grid : E.in_nat;
       pd.in.bstride = bin;
+      if (in_grid) pd.stream_in = 0;
     }
     if (i == np - 1) {
       pd.out = out_grid ? E.out_grid : E.out_nat;

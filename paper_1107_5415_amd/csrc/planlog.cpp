@@ -38,10 +38,11 @@ void log_engine(const LatticePlan* p, const Engine& E, const char* what) {
     // other kernels run the descriptor's stages
     char stages[32] = "";
     if (pd.kind != 2) std::snprintf(stages, sizeof stages, ", %d stages", pd.nst);
-    std::fprintf(stderr, "lfft:   %-8s pass %d/%d %s pencil %d x %d per tile%s, O=%d S=%d%s%s%s%s\n",
+    std::fprintf(stderr, "lfft:   %-8s pass %d/%d %s pencil %d x %d per tile%s, O=%d S=%d%s%s%s%s%s\n",
                  what, i + 1, np, pass_kernel_name(pd), pd.L, pd.W, stages, pd.O, pd.S,
                  pd.post ? ", four-step twiddle" : "", pd.in.mode == MAP_NATURAL ? ", natural in" : "",
                  pd.out.mode == MAP_NATURAL ? ", natural out" : "",
+                 pd.stream_in ? " (non-temporal loads)" : "",
                  pd.stream_out ? " (non-temporal stores)" : "");
   }
 }
