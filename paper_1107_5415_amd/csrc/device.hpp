@@ -57,7 +57,8 @@ struct PassDesc {
   // streaming kernel, last pass of a natural-order transform whose rows
   // pencils write whole aligned rows of the caller's output: stores marked
   // non-temporal, so that they do not evict the input and the intermediate
-  // grid from the caches
+  // grid from the caches; its loads of the intermediate grid (whole rows,
+  // dead once read) are non-temporal too
   int stream_out;
   // streaming kernel, first pass reading whole aligned rows of the caller's
   // natural-order input (read once by the call): loads marked non-temporal,

@@ -219,6 +219,20 @@ __device__ __forceinline__ long long xcd_tile(long long i, long long n) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// Non-temporal 8-byte load and store: the line is not kept for reuse.  For
+// data read or written once by a call (whole lines, so that no other wave
+// has to fetch the same line again), which leaves the caches to the data
+// that is read again.
+typedef float stream_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  const stream_f2 t = __builtin_nontemporal_load(reinterpret_cast<const stream_f2*>(p));
+  return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+  const stream_f2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<stream_f2*>(p));
+}
+
 // Natural box of a 2-D lattice, column Hermite form [[h00, h01], [0, h11]]:
 // c += b for reduced c and b.  c1 + b1 < 2 h11 needs at most one column-1
 // subtraction; c0 then lies in (-h00, 2 h00 - 1) and needs at most one

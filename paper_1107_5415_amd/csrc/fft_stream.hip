@@ -172,12 +172,13 @@ __device__ __forceinline__ void load_tile(float2* v, const PassDesc& p, const fl
     const int j = jt + TPP * q;
     side_positions<MIN, R>(A, p.in, p.S, j, L / R,
                            [&](int i, int off) {
-                             if constexpr (MIN == MAP_NATURAL && !COLS) {
-                               if (p.stream_in) {
-                                 typedef float nt_f2 __attribute__((ext_vector_type(2)));
-                                 const nt_f2 t = __builtin_nontemporal_load(
-                                     reinterpret_cast<const nt_f2*>(A.base + (unsigned)off));
-                                 v[q * R + i] = make_float2(t.x, t.y);
+                             // rows passes: non-temporal loads of the
+                             // caller's aligned input rows (first pass) or
+                             // of the intermediate grid, dead once read
+                             // (last pass of a reversed engine)
+                             if constexpr (!COLS) {
+                               if (MIN == MAP_NATURAL ? p.stream_in : p.stream_out) {
+                                 v[q * R + i] = load_stream(A.base + (unsigned)off);
                                  return;
                                }
                              }
@@ -366,9 +367,7 @@ __device__ __forceinline__ void store_tile(const float2* v, const PassDesc& p,
       }
       if constexpr (MOUT == MAP_NATURAL && !COLS) {
         if (p.stream_out) {
-          typedef float nt_f2 __attribute__((ext_vector_type(2)));
-          const nt_f2 v2 = {x.x, x.y};
-          __builtin_nontemporal_store(v2, reinterpret_cast<nt_f2*>(base + (unsigned)off));
+          store_stream(base + (unsigned)off, x);
         } else {
           base[(unsigned)off] = x;
         }

@@ -177,8 +177,9 @@ __global__ void __launch_bounds__(256) split_chain_kernel(SplitChain c, long lon
     float2 x0[NF - LEAF0], x1[NF - LEAF0];
 #pragma unroll
     for (int n = LEAF0; n < NF; ++n) {
-      x0[n - LEAF0] = ah[b * ah_bs + i0[n]];
-      x1[n - LEAF0] = ah[b * ah_bs + i1[n]];
+      // the finest input is dead once read
+      x0[n - LEAF0] = lfft::dev::load_stream(&ah[b * ah_bs + i0[n]]);
+      x1[n - LEAF0] = lfft::dev::load_stream(&ah[b * ah_bs + i1[n]]);
     }
     float2 lo[NF];
 #pragma unroll
@@ -226,10 +227,11 @@ __global__ void __launch_bounds__(256) unsplit_chain_kernel(SplitChain c, long l
 #pragma unroll
     for (int n = 0; n < NF; ++n) {
       const int j = K - 1 - node_depth(n);
-      y2[n] = c.d2[j][b * c.d2_bs[j] + kk[n]];
+      // the channels and the coarsest low-pass are dead once read
+      y2[n] = lfft::dev::load_stream(&c.d2[j][b * c.d2_bs[j] + kk[n]]);
     }
     float2 lo[NF];
-    lo[0] = d1[b * d1_bs + t];
+    lo[0] = lfft::dev::load_stream(&d1[b * d1_bs + t]);
 #pragma unroll
     for (int n = 0; n < NF; ++n) {
       const float2 y1 = lo[n];
