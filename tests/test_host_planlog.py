@@ -39,10 +39,15 @@ def test_log_prints_the_schedule():
     # the two forward passes of the large workload: rows over the 8192-cycle
     # from the natural samples, then 8-column tiles onto natural frequencies
     assert any("forward  pass 1/2 fft_stream_kernel<8192, 1, false, false, 2, 0>" in l
-               for l in lines), err
+               and "(non-temporal loads)" in l for l in lines), err
     assert any("forward  pass 2/2 fft_stream_kernel<2048, 8, true, false, 0, 2>" in l
                for l in lines), err
-    assert any("inverse  pass 2/2" in l and "natural out" in l for l in lines), err
+    # the inverse ends with rows onto the aligned samples: streamed stores
+    assert any("inverse  pass 2/2" in l and "natural out (non-temporal stores)" in l
+               for l in lines), err
+    # column passes never stream (two tiles share each cache line)
+    assert not any("true, " in l.split("fft_stream_kernel<")[-1][:20] and "non-temporal" in l
+                   for l in lines if "fft_stream_kernel<" in l), err
     assert any(l.startswith("lfft: pyramid d=2 m=16777216") and "q=2 levels=3" in l
                for l in lines), err
     assert sum("  level " in l for l in lines) == 3
