@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) split_q_kernel(SplitQDesc sd, long long b
     float2 x[QM];
 #pragma unroll
     for (int l = 0; l < QM; ++l)
-      if (l < q) x[l] = ah[b * ah_bs + idx[l]];
+      if (l < q) x[l] = lfft::dev::load_stream(&ah[b * ah_bs + idx[l]]);  // dead once read
     float2 y0 = make_float2(0.f, 0.f);
 #pragma unroll
     for (int l = 0; l < QM; ++l)
@@ -335,11 +335,12 @@ __global__ void __launch_bounds__(256) unsplit_q_kernel(SplitQDesc sd, long long
   reflector<Q>(sd, mask, idx, u, sigma, v0, c);
   for (long long b = 0; b < batch; ++b) {
     float2 y[QM];
-    y[0] = d0[b * d0_bs + k];
+    // the channels are dead once read
+    y[0] = lfft::dev::load_stream(&d0[b * d0_bs + k]);
     const float2* in = dw + b * dw_bs + k;
 #pragma unroll
     for (int j = 1; j < QM; ++j)
-      if (j < q) y[j] = in[(j - 1) * sd.mN];
+      if (j < q) y[j] = lfft::dev::load_stream(&in[(j - 1) * sd.mN]);
     float2 tau = make_float2(0.f, 0.f);
 #pragma unroll
     for (int j = 1; j < QM; ++j)
