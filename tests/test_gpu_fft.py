@@ -79,6 +79,11 @@ CASES = [
     ("chirp_z_plus_axis_d3", ((2, 0, 0), (0, 2, 0), (0, 0, 8209)), 2),
     ("chirp_z_sheared", ((8209, 1), (0, 3)), 1),
     ("chirp_z_lower", ((8209, 0), (5, 8)), 1),
+    # streaming passes over several signals with non-temporal row accesses:
+    # loads on the forward's first pass and stores on the inverse's last
+    # (forward-aligned), and the mirror order (inverse-aligned)
+    ("streaming_batch3_upper_2^22", ((2048, 1024), (0, 2048)), 3),
+    ("streaming_batch2_lower_2^22", ((2048, 0), (1024, 2048)), 2),
 ]
 
 
