@@ -60,6 +60,32 @@ def test_log_prints_the_schedule():
     assert "forward  pass 2/2 fft_stream_kernel<8192, 1, false, false, 0, 2>" in lines[i + 2], err
 
 
+CHILD_CYCLES = r"""
+import sys
+sys.path.insert(0, %r)
+from paper_1107_5415_amd import lfft
+for n in (1 << 27, 1 << 30, 5 << 26):
+    lfft.LatticePlan(((n,),), host_only=True)
+""" % ROOT
+
+
+def test_long_cycles_split_in_three_balanced_digits():
+    """Cycles beyond two pencils split into three on-chip digits whose
+    natural-order tables (two digits each) stay within 2^20 entries:
+    2^27 = 512^3, 2^30 = 1024^3, 5 * 2^26 = 512 * 512 * 1280."""
+    env = dict(os.environ, LFFT_LOG="1")
+    r = subprocess.run([sys.executable, "-c", CHILD_CYCLES], env=env, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    plans = []
+    for l in r.stderr.splitlines():
+        if l.startswith("lfft: plan"):
+            plans.append([])
+        elif "forward  pass" in l:
+            plans[-1].append(int(l.split(" pencil ")[1].split(" x ")[0]))
+    assert plans == [[512, 512, 512], [1024, 1024, 1024], [512, 512, 1280]], r.stderr
+
+
 def test_log_is_silent_by_default():
     assert "lfft:" not in run(None)
     assert "lfft:" not in run("0")
